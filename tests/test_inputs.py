@@ -1,0 +1,136 @@
+"""Pins on the input generators: GLL nodes, the differentiation matrix,
+metric terms and the hydrostatic reference state (all closed forms or
+invariants, independent of both the oracle and the HIP path)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1604_08501_amd import inputs as I
+
+
+@pytest.mark.parametrize("N,expected", [
+    (1, [-1.0, 1.0]),
+    (2, [-1.0, 0.0, 1.0]),
+    (3, [-1.0, -1.0 / math.sqrt(5.0), 1.0 / math.sqrt(5.0), 1.0]),
+    (4, [-1.0, -math.sqrt(3.0 / 7.0), 0.0, math.sqrt(3.0 / 7.0), 1.0]),
+    # N=5: interior roots of P_5' are +-sqrt(1/3 -+ 2 sqrt(7)/21)
+    (5, [-1.0, -math.sqrt(1 / 3 + 2 * math.sqrt(7) / 21), -math.sqrt(1 / 3 - 2 * math.sqrt(7) / 21),
+         math.sqrt(1 / 3 - 2 * math.sqrt(7) / 21), math.sqrt(1 / 3 + 2 * math.sqrt(7) / 21), 1.0]),
+])
+def test_gll_closed_form(N, expected):
+    np.testing.assert_allclose(I.gll_nodes(N), expected, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("N", range(1, 16))
+def test_gll_symmetric_and_quadrature(N):
+    x = I.gll_nodes(N)
+    w = I.gll_weights(N)
+    assert np.all(np.diff(x) > 0)
+    np.testing.assert_allclose(x, -x[::-1], atol=1e-15)
+    # GLL quadrature is exact for degree <= 2N - 1
+    for m in range(0, 2 * N):
+        exact = 0.0 if m % 2 else 2.0 / (m + 1)
+        assert abs(np.dot(w, x ** m) - exact) < 1e-13
+
+
+@pytest.mark.parametrize("N", range(1, 16))
+def test_diff_matrix_exact_on_polynomials(N):
+    x = I.gll_nodes(N)
+    D = I.diff_matrix(N)
+    for m in range(0, N + 1):
+        dexact = m * x ** (m - 1) if m > 0 else np.zeros_like(x)
+        assert np.max(np.abs(D @ x ** m - dexact)) < 1e-13 * max(1, N * N)
+    assert np.max(np.abs(D.sum(axis=1))) < 1e-13
+    # corner entries and centro-antisymmetry of the GLL derivative matrix
+    assert abs(D[0, 0] + N * (N + 1) / 4.0) < 1e-12 * N * N
+    assert abs(D[N, N] - N * (N + 1) / 4.0) < 1e-12 * N * N
+    np.testing.assert_allclose(D[::-1, ::-1], -D, atol=1e-12 * N * N)
+    # D^(N+1) annihilates every polynomial of degree N: it is nilpotent
+    P = np.linalg.matrix_power(D, N + 1)
+    assert np.max(np.abs(P)) < 1e-9 * np.max(np.abs(D)) ** (N + 1)
+
+
+def test_affine_metric_identities():
+    rng = np.random.default_rng(0)
+    mesh = I.affine_mesh(3, rng, n_side=2)
+    g = mesh.geo
+    for e in range(mesh.Ne):
+        A = mesh.A[e, 0]
+        J = np.linalg.det(A)
+        assert J > 0
+        G = np.array([[g[e, 3 * d + a, 0] for d in range(3)] for a in range(3)])   # G[a, d]
+        # sum_a g_ad A_ae = J delta_de
+        np.testing.assert_allclose(G.T @ A, J * np.eye(3), atol=1e-14)
+        np.testing.assert_allclose(g[e, 9], 1.0 / J, rtol=1e-14)
+        # affine: constant per element
+        assert np.ptp(g[e], axis=1).max() < 1e-15
+        # g = J * (dxi/dx)^T, i.e. g[a, d] = J * inv(A)[d, a]
+        np.testing.assert_allclose(G, J * np.linalg.inv(A).T, rtol=1e-13, atol=1e-15)
+
+
+def _warp_map(e, xi, n=32, L=1000.0, w=0.05):
+    """Physical position of reference point xi = (r, s, t) in element e."""
+    ex, ey, ez = e % n, (e // n) % n, e // (n * n)
+    X = (ex + 0.5 * (xi[0] + 1)) / n
+    Y = (ey + 0.5 * (xi[1] + 1)) / n
+    Z = (ez + 0.5 * (xi[2] + 1)) / n
+    s = np.sin
+    p = np.pi
+    return L * np.array([X + w * s(p * Y) * s(p * Z), Y + w * s(p * Z) * s(p * X),
+                         Z + w * s(p * X) * s(p * Y)])
+
+
+def test_warped_metric_matches_map_derivative():
+    """The analytic per-node Jacobian of the warped map agrees with a
+    centred difference of the map, and its cofactor satisfies
+    sum_a g_ad A_ae = J delta_de with J > 0."""
+    N = 4
+    Nq = N + 1
+    els = np.array([0, 1, 33, 1057, 32767])
+    mesh = I.warped_mesh(N, 32, els)
+    x = I.gll_nodes(N)
+    h = 1e-5
+    for ie, e in enumerate(els):
+        for m in (0, 7, 31, 62, 124):
+            xi = np.array([x[m % Nq], x[(m // Nq) % Nq], x[m // (Nq * Nq)]])
+            np.testing.assert_allclose(mesh.xyz[ie, :, m], _warp_map(e, xi), rtol=1e-14)
+            for d in range(3):
+                dx = np.zeros(3)
+                dx[d] = h
+                fd = (_warp_map(e, xi + dx) - _warp_map(e, xi - dx)) / (2 * h)
+                np.testing.assert_allclose(mesh.A[ie, m, :, d], fd, rtol=1e-8, atol=1e-7)
+    g = mesh.geo
+    Gm = np.stack([np.stack([g[:, 3 * d + a] for d in range(3)], -1) for a in range(3)], -2)  # (Ne,M,a,d)
+    prod = np.einsum("xmad,xmaf->xmdf", Gm, mesh.A)
+    J = 1.0 / g[:, 9]
+    assert np.all(J > 0)
+    np.testing.assert_allclose(prod, J[..., None, None] * np.eye(3), rtol=1e-12, atol=1e-9)
+
+
+def test_hydrostatic_reference():
+    z = np.linspace(0.0, 1000.0, 101)
+    rho, Theta, p = I.hydrostatic_reference(z)
+    # EOS of the reference state reproduces p_ref
+    np.testing.assert_allclose(I.P0 * (I.R_GAS * Theta / I.P0) ** I.GAMMA, p, rtol=1e-13)
+    # hydrostatic balance dp/dz = -rho g (centred difference of the closed form)
+    hh = 1e-3
+    dp = (I.hydrostatic_reference(z + hh)[2] - I.hydrostatic_reference(z - hh)[2]) / (2 * hh)
+    np.testing.assert_allclose(dp, -rho * I.GRAV, rtol=1e-7)
+    assert abs(rho[0] - I.RHO_SURF) < 1e-14
+    np.testing.assert_allclose(Theta / rho, I.THETA0, rtol=1e-14)
+
+
+def test_workload_draws_are_reproducible():
+    a = I.affine_workload()
+    b = I.affine_workload()
+    assert np.array_equal(a.q, b.q) and np.array_equal(a.geo, b.geo)
+    assert a.q.shape == (64, 5, 125) and a.geo.shape == (64, 10, 125)
+    w = I.warped_workload(n_elements=8)
+    full = I.warped_workload(n_side=32, n_elements=16)
+    # the element subset of the mesh agrees with the full mesh
+    assert np.array_equal(w.geo, full.geo[:8])
+    rho = a.q[:, 0]
+    assert 0.9 < rho.min() and rho.max() < 1.1
+    theta = a.q[:, 4] / rho
+    assert 290 < theta.min() and theta.max() < 310
