@@ -1,0 +1,190 @@
+"""Benchmark: volume-RHS elements/s and GFLOP/s at N=7, FP64 and FP32.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the warped 32^3 box at N=7 (Nq=8, 512 nodes per element), 32768
+curvilinear elements, 5 fields, D along r, s and t, gravity source and
+reference-state pressure.  One step = one evaluation of the whole volume
+term (one kernel launch over all elements) with inputs resident in HBM.
+``value`` is the FP64 rate; the FP32 form of the same workload is reported
+beside it, with its error against the FP64 oracle and the FP32/FP64 speedup.
+
+Prints one JSON line.  ``roofline`` prices the FP64 volume kernel against
+the 8 TB/s HBM peak using the algorithmic bytes per node (176 B in FP64,
+92 B in FP32); its duration is measured with HIP events on the launch
+stream.  ``cpu_baseline`` times the CPU oracle on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_NODE = {"f64": 176, "f32": 92}
+
+
+def flops_per_node(Nq: int) -> int:
+    # 3 directions x 5 fields x Nq FMAs (2 FLOP each) + pointwise work
+    # (1/rho 1, EOS/perturbation 6, fluxes 3 x 16, 1/J 5, source 3)
+    return 30 * Nq + 63
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1604_08501_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".inc", ".hpp", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_key: str):
+    """HBM bytes per launch from the committed PMC summary, if it was taken
+    on the current kernel sources (else None)."""
+    p = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        d = json.load(open(p))
+    except (OSError, ValueError):
+        return None
+    ent = d.get(kernel_key)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def time_launches(fn, steps: int, warmup: int, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    for _ in range(steps):
+        fn()
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(end) / steps, wall
+
+
+def cpu_baseline(w, budget_s: float):
+    import oracle
+    phys = w.phys.as_tuple()
+    out = np.empty_like(w.q)
+    oracle.volume_rhs(w.D, w.geo, w.q, w.rho_ref, w.theta_ref, phys, out=out)   # warm-up
+    n, t0 = 0, time.perf_counter()
+    while True:
+        oracle.volume_rhs(w.D, w.geo, w.q, w.rho_ref, w.theta_ref, phys, out=out)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return {"value": n * w.Ne / el, "unit": "elements/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle over the full N=7 warped mesh ({w.Ne} elements), "
+                      f"{n} passes in {el:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    a = ap.parse_args(argv)
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the volume term has no cross-GPU exchange, "
+              "so a multi-GPU run is not part of this benchmark", file=sys.stderr)
+        return 2
+
+    import torch
+    import oracle
+    import paper_1604_08501_amd as sv
+    from paper_1604_08501_amd import inputs as I
+
+    sv.lib()   # raises if the HIP library is missing
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    t0 = time.perf_counter()
+    w = I.warped_workload()                      # N=7, 32768 elements, seed k=2
+    Ne, Nq = w.Ne, w.Nq
+    nodes = Ne * Nq ** 3
+    print(f"# generated workload in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    phys = w.phys.as_tuple()
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+    results = {}
+    ref64 = oracle.volume_rhs(w.D, w.geo, w.q, w.rho_ref, w.theta_ref, phys)
+    for tag, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        src = w if dt == torch.float64 else I.to_fp32(w)
+        q, geo, D = dev(src.q), dev(src.geo), dev(src.D)
+        rr, tr = dev(src.rho_ref), dev(src.theta_ref)
+        out = torch.empty_like(q)
+        fn = lambda: sv.volume_rhs(q, geo, D, rr, tr, phys, out=out)
+        fn()
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        ref = ref64 if tag == "f64" else oracle.volume_rhs(
+            *(np.asarray(x, np.float64) for x in (src.D, src.geo, src.q, src.rho_ref)),
+            src.theta_ref, phys)
+        err = float(I.rel_err_per_field(got, ref).max())
+        ms, wall = time_launches(fn, a.steps, a.warmup, stream)
+        bytes_launch = BYTES_PER_NODE[tag] * nodes
+        results[tag] = dict(ms=ms, wall=wall, err=err, bytes=bytes_launch,
+                            el_s=Ne / (ms * 1e-3), gbs=bytes_launch / (ms * 1e-3) / 1e9,
+                            gflops=flops_per_node(Nq) * nodes / (ms * 1e-3) / 1e9)
+        print(f"# {tag}: {ms * 1e3:.1f} us/launch, {results[tag]['gbs']:.0f} GB/s, "
+              f"err {err:.2e}", file=sys.stderr, flush=True)
+        del q, geo, D, rr, tr, out
+        torch.cuda.empty_cache()
+
+    r64, r32 = results["f64"], results["f32"]
+    traffic = measured_traffic("volume_f64_n7")
+    line = {
+        "metric": "volume-RHS elements/s at N=7 (FP64; FP32 beside it), error vs FP64 oracle",
+        "value": r64["el_s"],
+        "unit": "elements/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": r64["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded warped 32^3 mesh, random state about a hydrostatic reference)",
+        "config": {"workload": "strong-form SEM volume RHS, N=7 (Nq=8), 32768 warped hex "
+                               "elements, 5 fields, r+s+t, gravity, perturbation pressure",
+                   "N": 7, "Ne": Ne, "nodes": nodes},
+        "gflops": r64["gflops"],
+        "err_fp64": r64["err"],
+        "fp32": {"value": r32["el_s"], "unit": "elements/s", "ms_per_step": r32["ms"],
+                 "gflops": r32["gflops"], "err_vs_fp64_oracle": r32["err"],
+                 "roofline": {"bound": "hbm", "achieved": r32["gbs"], "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": r32["gbs"] / HBM_PEAK_GBS,
+                              "traffic": measured_traffic("volume_f32_n7")}},
+        "speedup_fp32_vs_fp64": r64["ms"] / r32["ms"],
+        "roofline": {"bound": "hbm", "achieved": r64["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r64["gbs"] / HBM_PEAK_GBS, "traffic": traffic},
+    }
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

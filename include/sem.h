@@ -1,0 +1,216 @@
+/*
+ * semvol — the strong-form spectral-element volume term of the dry-atmosphere
+ * Euler equations on one AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the one of Sec. 2 of Klöckner, Wilcox, Warburton, "Array
+ * Program Transformation with Loo.py by Example: High-Order Finite Elements"
+ * (ARRAY'16): the volume contribution v of Eq. (volterm) to the method-of-lines
+ * rate dq/dt = v(q) + s(q), for hexahedral elements of Nq^3 Gauss-Lobatto
+ * nodes, with the flux column of equation set 2C and the equation of state
+ * p = p0 (R Theta / p0)^gamma (Sec. 2).  This library adds a gravity source,
+ * a reference-state (perturbation) pressure, an FP32 form, a vector-Jacobian
+ * product, a mixed-order batched launch and an SSP-RK3 step captured in a
+ * HIP graph.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *   Nq            nodes per direction (polynomial order N = Nq - 1); supported
+ *                 2 <= Nq <= 10.
+ *   node index    m = i + Nq*j + Nq^2*k, with i, j, k along the reference
+ *                 directions r, s, t (Fig. 1 of the paper).
+ *   D             [Nq][Nq], D[i*Nq + n] = l_n'(xi_i): row i is the output node.
+ *   geo           [Ne][10][Nq^3]: slot 3*d + a holds g_{a d} = J * dxi_d/dx_a
+ *                 (a, d = 0..2; slots 0-2 serve the r sum, 3-5 the s sum, 6-8
+ *                 the t sum, as in the listed r/s kernels), slot 9 holds 1/J.
+ *   q, rhs        [Ne][5][Nq^3]: rho, U1 = rho u, U2 = rho v, U3 = rho w,
+ *                 Theta = rho theta (the order of the prognostic vector).
+ *   rho_ref       [Ne][Nq^3], same dtype as q, or NULL.
+ *   theta_ref     [Ne][Nq^3], ALWAYS FP64, or NULL.  rho_ref and theta_ref are
+ *                 both NULL or both given.
+ *   dtype         SEM_F64: every array FP64.  SEM_F32: D, geo, q, rho_ref,
+ *                 rhs, lambda, mu FP32; theta_ref stays FP64.
+ *
+ * The computed volume term (readings of Sec. 2 where it is silent):
+ *   v_b(i,j,k) = -(1/J(i,j,k)) sum_{n,a} [ D[i][n] g_a0(n,j,k) f_ab(n,j,k)
+ *                                        + D[j][n] g_a1(i,n,k) f_ab(i,n,k)
+ *                                        + D[k][n] g_a2(i,j,n) f_ab(i,j,n) ]
+ *   v_U3      += -grav * (rho - rho_ref)
+ * with f_a the flux column of set 2C (5 fields) and the pressure in f replaced
+ * by p - p_ref, p_ref = p0 (R Theta_ref / p0)^gamma, when a reference is given
+ * (rho_ref = 0 and p_ref = 0 otherwise).  The sign is the one of the listed
+ * kernels and of dq/dt = -div f (Eq. (volterm) prints "+").
+ *
+ * Memory and streams: every array argument is a DEVICE pointer owned by the
+ * caller and must stay valid until the enqueued work has finished.  Pointers
+ * must be aligned to their element size.  `stream` is a hipStream_t (NULL =
+ * the null stream).  Calls only enqueue work; none synchronises except
+ * sem_batch_plan and sem_rk3_graph_create when they autotune.
+ *
+ * Errors: every entry point returns a sem_status.  Arguments are validated on
+ * the host before any HIP call; on failure nothing is enqueued and
+ * sem_last_error() returns a message.  A failed kernel launch returns
+ * SEM_ERR_HIP.  Numerical domain errors (rho = 0, Theta <= 0) are not
+ * checked: NaN/Inf propagate to the outputs of the affected element.
+ */
+#ifndef SEMVOL_SEM_H
+#define SEMVOL_SEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sem_status {
+    SEM_OK = 0,
+    SEM_ERR_INVALID_ARG = -1,   /* bad size, NULL or misaligned pointer, bad dtype */
+    SEM_ERR_UNSUPPORTED = -2,   /* Nq or tile shape not compiled in */
+    SEM_ERR_HIP = -3,           /* a HIP runtime call or kernel launch failed */
+    SEM_ERR_NO_MEMORY = -4      /* host or device allocation failed (plans, graphs) */
+} sem_status;
+
+typedef enum sem_dtype { SEM_F64 = 0, SEM_F32 = 1 } sem_dtype;
+
+/* Physical constants: the paper's kernel arguments p_p0, p_Gamma, p_R
+ * (reference pressure, ratio of specific heats, gas constant), plus the
+ * gravitational acceleration of the source term. */
+typedef struct sem_phys {
+    double p0;
+    double gamma;
+    double R;
+    double grav;
+} sem_phys;
+
+/* Tile shape of the single-order kernels: elements per workgroup.
+ * 0 selects the built-in default for (dtype, Nq). */
+typedef struct sem_tile {
+    int32_t elems_per_block;
+    int32_t reserved;
+} sem_tile;
+
+/* Thread-local text describing the last non-OK status of this thread. */
+const char* sem_last_error(void);
+
+/* Library version string. */
+const char* sem_version(void);
+
+/*
+ * Volume term of Eq. (volterm) plus the gravity source, for Ne elements of
+ * one order (the argument list of the paper's refFluxR/refFluxS kernels,
+ * (Ne, Nq, geo, D, q, rhsq, p_p0, p_Gamma, p_R), extended by dtype, the
+ * reference state, gravity and a stream).
+ *   rhs = v(q)            if accumulate == 0
+ *   rhs = rhs + v(q)      otherwise (the paper's rhsq update semantics)
+ * rhs must not alias q, geo, D or the reference arrays.
+ * Errors: Ne < 1 (the paper's assumption Ne >= 1), unsupported Nq, NULL
+ * required pointer, only one of rho_ref/theta_ref, misaligned pointer,
+ * unknown dtype -> SEM_ERR_INVALID_ARG / SEM_ERR_UNSUPPORTED before any HIP
+ * call.  Allocates nothing.
+ */
+sem_status sem_volume_rhs(int32_t Ne, int32_t Nq, sem_dtype dtype,
+                          const void* D, const void* geo, const void* q,
+                          const void* rho_ref, const double* theta_ref,
+                          const sem_phys* phys, void* rhs, int32_t accumulate,
+                          void* stream);
+
+/* As sem_volume_rhs, with an explicit tile shape (NULL = default).  An
+ * elems_per_block value that is not compiled for (dtype, Nq) returns
+ * SEM_ERR_UNSUPPORTED. */
+sem_status sem_volume_rhs_tiled(int32_t Ne, int32_t Nq, sem_dtype dtype,
+                                const void* D, const void* geo, const void* q,
+                                const void* rho_ref, const double* theta_ref,
+                                const sem_phys* phys, void* rhs, int32_t accumulate,
+                                const sem_tile* tile, void* stream);
+
+/* Writes up to `cap` supported elems_per_block values for (dtype, Nq) into
+ * `out` and returns how many exist (0 for an unsupported Nq). */
+int32_t sem_tile_options(sem_dtype dtype, int32_t Nq, int32_t* out, int32_t cap);
+
+/*
+ * Vector-Jacobian product of the volume term with respect to the state
+ * (derivative of the flux column and EOS of Sec. 2):
+ *   mu = (dv/dq)^T lambda        (mu += ... if accumulate != 0)
+ * The reference state does not enter: d(p - p_ref)/dTheta = dp/dTheta.
+ * lambda, mu: [Ne][5][Nq^3], dtype.  mu must not alias the inputs.
+ * Errors as for sem_volume_rhs.  Allocates nothing.
+ */
+sem_status sem_volume_rhs_adjoint(int32_t Ne, int32_t Nq, sem_dtype dtype,
+                                  const void* D, const void* geo, const void* q,
+                                  const sem_phys* phys, const void* lambda, void* mu,
+                                  int32_t accumulate, void* stream);
+
+/* out[i] = a*x[i] + b*(y[i] + c*z[i]) for i < n (x may be NULL when a == 0);
+ * the stage update of an explicit Runge-Kutta method.  out may alias x or y.
+ * Errors: n < 0, NULL required pointer, misalignment. */
+sem_status sem_axpby(int64_t n, sem_dtype dtype, double a, const void* x, double b,
+                     const void* y, double c, const void* z, void* out, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Mixed-order batch: many element blocks, each of one order, evaluated by ONE
+ * persistent kernel launch.  A block has the layouts above with its own Nq and
+ * Ne; every block of a plan shares dtype and phys.
+ * ------------------------------------------------------------------------- */
+typedef struct sem_block {
+    int32_t Nq;
+    int32_t Ne;
+    const void* D;
+    const void* geo;
+    const void* q;
+    const void* rho_ref;       /* nullable */
+    const double* theta_ref;   /* nullable, FP64 */
+    void* rhs;
+} sem_block;
+
+typedef struct sem_plan_s* sem_plan;
+
+#define SEM_PLAN_AUTOTUNE 1u   /* time candidate tile shapes on the device (synchronises) */
+#define SEM_PLAN_USE_CACHE 2u  /* read/write tuned shapes in the JSON file named by the
+                                  SEM_PLAN_CACHE environment variable (ignored if unset) */
+
+/* Builds a plan: picks a tile shape per order (autotuned or default), orders
+ * the tiles longest-first and uploads a device tile table owned by the plan.
+ * The block pointers are baked in: the caller keeps those buffers alive and
+ * unchanged in address for the plan's lifetime.  Errors: nblocks < 1, any
+ * invalid block (as sem_volume_rhs), SEM_ERR_NO_MEMORY, SEM_ERR_HIP. */
+sem_status sem_batch_plan(const sem_block* blocks, int32_t nblocks, sem_dtype dtype,
+                          const sem_phys* phys, uint32_t flags, void* stream,
+                          sem_plan* out);
+
+/* Enqueues the whole batch as one persistent launch: rhs of every block =
+ * v(q) of that block.  Allocates nothing. */
+sem_status sem_batch_execute(sem_plan plan, void* stream);
+
+/* Writes a JSON description of the plan's choices (NUL-terminated, truncated
+ * to len).  Returns SEM_ERR_INVALID_ARG for a NULL plan or buffer. */
+sem_status sem_plan_describe(sem_plan plan, char* buf, int32_t len);
+
+/* Frees the plan and its device tables (after the enqueued work finished). */
+sem_status sem_plan_destroy(sem_plan plan);
+
+/* ---------------------------------------------------------------------------
+ * One SSP-RK3 (Shu-Osher) step of dq/dt = v(q), captured once in a HIP graph:
+ *   q1 = q + dt v(q);  q2 = 3/4 q + 1/4 (q1 + dt v(q1));
+ *   q  = 1/3 q + 2/3 (q2 + dt v(q2))          (q updated in place)
+ * Each stage is one persistent batch launch plus one sem_axpby.
+ * q_n, q_1, q_2, L are flat buffers of n values of dtype; every block's q
+ * must lie inside q_n and its rhs inside L at the same offset (the stage
+ * plans read q_1 and q_2 at that offset).  L receives the last stage's rate.
+ * ------------------------------------------------------------------------- */
+typedef struct sem_rk3_s* sem_rk3;
+
+sem_status sem_rk3_graph_create(const sem_block* blocks, int32_t nblocks, sem_dtype dtype,
+                                const sem_phys* phys, uint32_t flags, void* q_n, void* q_1,
+                                void* q_2, void* L, int64_t n, double dt, void* stream,
+                                sem_rk3* out);
+
+/* Launches the captured step on `stream`.  Allocates nothing. */
+sem_status sem_rk3_graph_launch(sem_rk3 step, void* stream);
+
+/* Frees the graph and its three stage plans. */
+sem_status sem_rk3_graph_destroy(sem_rk3 step);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEMVOL_SEM_H */

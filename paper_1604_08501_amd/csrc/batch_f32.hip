@@ -1,0 +1,3 @@
+// Persistent batch kernel, float instantiation.
+#define SEM_REAL float
+#include "batch.inc"

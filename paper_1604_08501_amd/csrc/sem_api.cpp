@@ -1,0 +1,981 @@
+// C-ABI of libsem.so: argument validation, status codes, tile selection,
+// batch plans (autotuner, plan cache, device tile tables) and the SSP-RK3
+// step captured in a HIP graph.  The operations themselves are documented
+// in include/sem.h; the kernels live in kernels_*.hip and batch_*.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cerrno>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sem.h"
+#include "sem_internal.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sem_status fail(sem_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+sem_status hip_fail(hipError_t err, const char* what)
+{
+    return fail(SEM_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(err), (int)err);
+}
+
+bool log_enabled()
+{
+    static int on = -1;
+    if (on < 0) {
+        const char* v = getenv("SEM_LOG");
+        on = (v && *v && strcmp(v, "0") != 0) ? 1 : 0;
+    }
+    return on == 1;
+}
+
+size_t elem_size(sem_dtype dt) { return dt == SEM_F64 ? 8 : 4; }
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+semk::Phys to_phys(const sem_phys* p)
+{
+    return semk::Phys{p->p0, p->gamma, p->R, p->grav, p->R / p->p0};
+}
+
+constexpr int kMinNq = 2, kMaxNq = 10;
+
+// Built-in tile shapes for the single-order kernels: about 256 threads for
+// small orders, one element per workgroup from Nq = 6 on.
+int default_epb(int nq)
+{
+    switch (nq) {
+    case 2: return 32;
+    case 3: return 8;
+    case 4: return 4;
+    case 5: return 2;
+    default: return 1;
+    }
+}
+
+sem_status check_dtype(sem_dtype dt)
+{
+    if (dt != SEM_F64 && dt != SEM_F32)
+        return fail(SEM_ERR_INVALID_ARG, "unknown dtype %d", (int)dt);
+    return SEM_OK;
+}
+
+sem_status check_order(int32_t Ne, int32_t Nq)
+{
+    if (Ne < 1)
+        return fail(SEM_ERR_INVALID_ARG, "Ne = %d: at least one element is required", Ne);
+    if (Nq < kMinNq || Nq > kMaxNq)
+        return fail(SEM_ERR_UNSUPPORTED, "Nq = %d is not compiled (supported %d..%d)", Nq, kMinNq,
+                    kMaxNq);
+    return SEM_OK;
+}
+
+sem_status check_ptr(const void* p, size_t align, const char* name, bool required = true)
+{
+    if (!p)
+        return required ? fail(SEM_ERR_INVALID_ARG, "%s is NULL", name) : SEM_OK;
+    if (!aligned(p, align))
+        return fail(SEM_ERR_INVALID_ARG, "%s = %p is not %zu-byte aligned", name, p, align);
+    return SEM_OK;
+}
+
+#define SEM_TRY(expr)                 \
+    do {                              \
+        sem_status _st = (expr);      \
+        if (_st != SEM_OK)            \
+            return _st;               \
+    } while (0)
+
+sem_status check_volume_args(int32_t Ne, int32_t Nq, sem_dtype dt, const void* D, const void* geo,
+                             const void* q, const void* rho_ref, const double* theta_ref,
+                             const sem_phys* phys, const void* rhs)
+{
+    SEM_TRY(check_dtype(dt));
+    SEM_TRY(check_order(Ne, Nq));
+    if (!phys)
+        return fail(SEM_ERR_INVALID_ARG, "phys is NULL");
+    const size_t es = elem_size(dt);
+    SEM_TRY(check_ptr(D, es, "D"));
+    SEM_TRY(check_ptr(geo, es, "geo"));
+    SEM_TRY(check_ptr(q, es, "q"));
+    SEM_TRY(check_ptr(rhs, es, "rhs"));
+    if ((rho_ref == nullptr) != (theta_ref == nullptr))
+        return fail(SEM_ERR_INVALID_ARG, "rho_ref and theta_ref must both be NULL or both be given");
+    SEM_TRY(check_ptr(rho_ref, es, "rho_ref", false));
+    SEM_TRY(check_ptr(theta_ref, 8, "theta_ref", false));
+    if (rhs == q || rhs == geo || rhs == D || rhs == rho_ref || rhs == (const void*)theta_ref)
+        return fail(SEM_ERR_INVALID_ARG, "rhs aliases an input array");
+    return SEM_OK;
+}
+
+template <typename T>
+semk::BlockPtrs<T> block_ptrs(int64_t Ne, const void* D, const void* geo, const void* q,
+                              const void* rho_ref, const double* theta_ref, void* rhs)
+{
+    return semk::BlockPtrs<T>{static_cast<const T*>(D),   static_cast<const T*>(geo),
+                              static_cast<const T*>(q),   static_cast<const T*>(rho_ref),
+                              theta_ref,                  static_cast<T*>(rhs),
+                              Ne};
+}
+
+int tile_options(sem_dtype dt, int nq, int* out, int cap)
+{
+    (void)dt;   // every compiled shape exists for both dtypes
+    int n = 0;
+    for (int i = 0; i < semh::kNumVariants; ++i)
+        if (semh::kVariants[i].nq == nq) {
+            if (n < cap && out)
+                out[n] = semh::kVariants[i].epb;
+            ++n;
+        }
+    return n;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Single-order entry points
+// ===========================================================================
+extern "C" const char* sem_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char* sem_version(void) { return "semvol 0.1.0 (gfx950)"; }
+
+extern "C" int32_t sem_tile_options(sem_dtype dtype, int32_t Nq, int32_t* out, int32_t cap)
+{
+    if (dtype != SEM_F64 && dtype != SEM_F32)
+        return 0;
+    return tile_options(dtype, Nq, out, cap);
+}
+
+extern "C" sem_status sem_volume_rhs_tiled(int32_t Ne, int32_t Nq, sem_dtype dtype, const void* D,
+                                           const void* geo, const void* q, const void* rho_ref,
+                                           const double* theta_ref, const sem_phys* phys, void* rhs,
+                                           int32_t accumulate, const sem_tile* tile, void* stream)
+{
+    SEM_TRY(check_volume_args(Ne, Nq, dtype, D, geo, q, rho_ref, theta_ref, phys, rhs));
+    int epb = tile && tile->elems_per_block > 0 ? tile->elems_per_block : default_epb(Nq);
+    if (semh::variant_index(Nq, epb) < 0)
+        return fail(SEM_ERR_UNSUPPORTED, "elems_per_block = %d is not compiled for Nq = %d", epb, Nq);
+    const semk::Phys ph = to_phys(phys);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t err;
+    if (dtype == SEM_F64)
+        err = semh::launch_volume<double>(
+            Nq, epb, block_ptrs<double>(Ne, D, geo, q, rho_ref, theta_ref, rhs), ph, accumulate, s);
+    else
+        err = semh::launch_volume<float>(
+            Nq, epb, block_ptrs<float>(Ne, D, geo, q, rho_ref, theta_ref, rhs), ph, accumulate, s);
+    if (err != hipSuccess)
+        return hip_fail(err, "volume kernel launch");
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_volume_rhs(int32_t Ne, int32_t Nq, sem_dtype dtype, const void* D,
+                                     const void* geo, const void* q, const void* rho_ref,
+                                     const double* theta_ref, const sem_phys* phys, void* rhs,
+                                     int32_t accumulate, void* stream)
+{
+    return sem_volume_rhs_tiled(Ne, Nq, dtype, D, geo, q, rho_ref, theta_ref, phys, rhs, accumulate,
+                                nullptr, stream);
+}
+
+extern "C" sem_status sem_volume_rhs_adjoint(int32_t Ne, int32_t Nq, sem_dtype dtype, const void* D,
+                                             const void* geo, const void* q, const sem_phys* phys,
+                                             const void* lambda, void* mu, int32_t accumulate,
+                                             void* stream)
+{
+    SEM_TRY(check_dtype(dtype));
+    SEM_TRY(check_order(Ne, Nq));
+    if (!phys)
+        return fail(SEM_ERR_INVALID_ARG, "phys is NULL");
+    const size_t es = elem_size(dtype);
+    SEM_TRY(check_ptr(D, es, "D"));
+    SEM_TRY(check_ptr(geo, es, "geo"));
+    SEM_TRY(check_ptr(q, es, "q"));
+    SEM_TRY(check_ptr(lambda, es, "lambda"));
+    SEM_TRY(check_ptr(mu, es, "mu"));
+    if (mu == q || mu == geo || mu == D || mu == lambda)
+        return fail(SEM_ERR_INVALID_ARG, "mu aliases an input array");
+    const int epb = default_epb(Nq);
+    const semk::Phys ph = to_phys(phys);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t err;
+    if (dtype == SEM_F64)
+        err = semh::launch_adjoint<double>(
+            Nq, epb,
+            semk::AdjPtrs<double>{static_cast<const double*>(D), static_cast<const double*>(geo),
+                                  static_cast<const double*>(q), static_cast<const double*>(lambda),
+                                  static_cast<double*>(mu), Ne},
+            ph, accumulate, s);
+    else
+        err = semh::launch_adjoint<float>(
+            Nq, epb,
+            semk::AdjPtrs<float>{static_cast<const float*>(D), static_cast<const float*>(geo),
+                                 static_cast<const float*>(q), static_cast<const float*>(lambda),
+                                 static_cast<float*>(mu), Ne},
+            ph, accumulate, s);
+    if (err != hipSuccess)
+        return hip_fail(err, "adjoint kernel launch");
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_axpby(int64_t n, sem_dtype dtype, double a, const void* x, double b,
+                                const void* y, double c, const void* z, void* out, void* stream)
+{
+    SEM_TRY(check_dtype(dtype));
+    if (n < 0)
+        return fail(SEM_ERR_INVALID_ARG, "n = %lld < 0", (long long)n);
+    const size_t es = elem_size(dtype);
+    SEM_TRY(check_ptr(x, es, "x", a != 0.0));
+    SEM_TRY(check_ptr(y, es, "y"));
+    SEM_TRY(check_ptr(z, es, "z"));
+    SEM_TRY(check_ptr(out, es, "out"));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t err;
+    if (dtype == SEM_F64)
+        err = semh::launch_axpby<double>(n, a, static_cast<const double*>(x), b,
+                                         static_cast<const double*>(y), c,
+                                         static_cast<const double*>(z), static_cast<double*>(out), s);
+    else
+        err = semh::launch_axpby<float>(n, a, static_cast<const float*>(x), b,
+                                        static_cast<const float*>(y), c,
+                                        static_cast<const float*>(z), static_cast<float*>(out), s);
+    if (err != hipSuccess)
+        return hip_fail(err, "axpby kernel launch");
+    return SEM_OK;
+}
+
+// ===========================================================================
+// Batch plans
+// ===========================================================================
+namespace {
+
+struct OrderChoice {
+    int nq = 0;
+    int epb = 0;
+    double us = -1.0;        // measured time of this order alone (autotuned), else -1
+    int64_t elements = 0;
+};
+
+struct PlanCore {
+    sem_dtype dtype = SEM_F64;
+    semk::Phys phys{};
+    int nt = 256;
+    int grid = 0;
+    int lds_bytes = 0;
+    int ntiles = 0;
+    int device = 0;
+    std::vector<sem_block> blocks;
+    std::vector<OrderChoice> orders;   // one per distinct Nq
+    semh::Tile* d_tiles = nullptr;
+    void* d_blocks = nullptr;
+    bool autotuned = false;
+    bool from_cache = false;
+};
+
+void free_core(PlanCore* p)
+{
+    if (!p)
+        return;
+    if (p->d_tiles)
+        (void)hipFree(p->d_tiles);
+    if (p->d_blocks)
+        (void)hipFree(p->d_blocks);
+    p->d_tiles = nullptr;
+    p->d_blocks = nullptr;
+}
+
+sem_status check_block(const sem_block& b, int idx, sem_dtype dt, const sem_phys* phys)
+{
+    sem_status st = check_volume_args(b.Ne, b.Nq, dt, b.D, b.geo, b.q, b.rho_ref, b.theta_ref, phys,
+                                      b.rhs);
+    if (st != SEM_OK) {
+        std::string m = g_last_error;
+        return fail(st, "block %d: %s", idx, m.c_str());
+    }
+    return SEM_OK;
+}
+
+template <typename T>
+std::vector<semk::BlockPtrs<T>> host_block_table(const std::vector<sem_block>& blocks)
+{
+    std::vector<semk::BlockPtrs<T>> v;
+    v.reserve(blocks.size());
+    for (const sem_block& b : blocks)
+        v.push_back(block_ptrs<T>(b.Ne, b.D, b.geo, b.q, b.rho_ref, b.theta_ref, b.rhs));
+    return v;
+}
+
+// Tiles of every block whose order is in `only_nq` (all if 0), sorted by
+// decreasing estimated cost (longest-processing-time first, stable).
+std::vector<semh::Tile> make_tiles(const std::vector<sem_block>& blocks,
+                                   const std::vector<OrderChoice>& orders, int only_nq)
+{
+    struct Item {
+        semh::Tile t;
+        double cost;
+    };
+    std::vector<Item> items;
+    for (size_t bi = 0; bi < blocks.size(); ++bi) {
+        const sem_block& b = blocks[bi];
+        if (only_nq && b.Nq != only_nq)
+            continue;
+        const OrderChoice* oc = nullptr;
+        for (const OrderChoice& o : orders)
+            if (o.nq == b.Nq)
+                oc = &o;
+        const int epb = oc->epb;
+        const int vid = semh::variant_index(b.Nq, epb);
+        const double nodes = (double)b.Nq * b.Nq * b.Nq;
+        // measured per-element time when autotuned, else a node count
+        const double per_elem = (oc->us > 0 && oc->elements > 0) ? oc->us / oc->elements : nodes;
+        for (int64_t e0 = 0; e0 < b.Ne; e0 += epb) {
+            const int ne = (int)std::min<int64_t>(epb, b.Ne - e0);
+            items.push_back({semh::Tile{(int32_t)bi, vid, ne, 0, e0}, per_elem * epb});
+        }
+    }
+    std::stable_sort(items.begin(), items.end(),
+                     [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    std::vector<semh::Tile> out;
+    out.reserve(items.size());
+    for (const Item& it : items)
+        out.push_back(it.t);
+    return out;
+}
+
+int lds_for(sem_dtype dt, int nt, const std::vector<OrderChoice>& orders, int only_nq)
+{
+    int lds = 0;
+    for (const OrderChoice& o : orders) {
+        if (only_nq && o.nq != only_nq)
+            continue;
+        const int b = dt == SEM_F64 ? semh::batch_lds_bytes<double>(nt, o.nq, o.epb)
+                                    : semh::batch_lds_bytes<float>(nt, o.nq, o.epb);
+        lds = std::max(lds, b);
+    }
+    return lds;
+}
+
+bool variant_ok(sem_dtype dt, int nt, int nq, int epb)
+{
+    return dt == SEM_F64 ? semh::batch_variant_ok<double>(nt, nq, epb)
+                         : semh::batch_variant_ok<float>(nt, nq, epb);
+}
+
+hipError_t occupancy(sem_dtype dt, int nt, int lds, int* bpc)
+{
+    return dt == SEM_F64 ? semh::batch_blocks_per_cu<double>(nt, lds, bpc)
+                         : semh::batch_blocks_per_cu<float>(nt, lds, bpc);
+}
+
+hipError_t launch(const PlanCore& p, const semh::Tile* d_tiles, int ntiles, int grid, int lds,
+                  hipStream_t s)
+{
+    if (p.dtype == SEM_F64)
+        return semh::launch_batch<double>(p.nt, d_tiles, ntiles,
+                                          static_cast<const semk::BlockPtrs<double>*>(p.d_blocks),
+                                          p.phys, grid, lds, s);
+    return semh::launch_batch<float>(p.nt, d_tiles, ntiles,
+                                     static_cast<const semk::BlockPtrs<float>*>(p.d_blocks), p.phys,
+                                     grid, lds, s);
+}
+
+// Upload the block table and the tile table for the current choices; fix
+// the grid from the occupancy of the chosen workgroup size and LDS.
+sem_status finalize(PlanCore& p, hipStream_t s)
+{
+    free_core(&p);
+    std::vector<semh::Tile> tiles = make_tiles(p.blocks, p.orders, 0);
+    p.ntiles = (int)tiles.size();
+    p.lds_bytes = lds_for(p.dtype, p.nt, p.orders, 0);
+    const size_t bt_bytes = p.blocks.size() *
+                            (p.dtype == SEM_F64 ? sizeof(semk::BlockPtrs<double>)
+                                                : sizeof(semk::BlockPtrs<float>));
+    hipError_t err = hipMalloc(&p.d_blocks, bt_bytes);
+    if (err != hipSuccess)
+        return fail(SEM_ERR_NO_MEMORY, "plan block table (%zu B): %s", bt_bytes,
+                    hipGetErrorString(err));
+    err = hipMalloc((void**)&p.d_tiles, tiles.size() * sizeof(semh::Tile));
+    if (err != hipSuccess)
+        return fail(SEM_ERR_NO_MEMORY, "plan tile table: %s", hipGetErrorString(err));
+    if (p.dtype == SEM_F64) {
+        auto hb = host_block_table<double>(p.blocks);
+        err = hipMemcpyAsync(p.d_blocks, hb.data(), bt_bytes, hipMemcpyHostToDevice, s);
+        if (err == hipSuccess)
+            err = hipStreamSynchronize(s);
+    } else {
+        auto hb = host_block_table<float>(p.blocks);
+        err = hipMemcpyAsync(p.d_blocks, hb.data(), bt_bytes, hipMemcpyHostToDevice, s);
+        if (err == hipSuccess)
+            err = hipStreamSynchronize(s);
+    }
+    if (err != hipSuccess)
+        return hip_fail(err, "upload block table");
+    err = hipMemcpyAsync(p.d_tiles, tiles.data(), tiles.size() * sizeof(semh::Tile),
+                         hipMemcpyHostToDevice, s);
+    if (err == hipSuccess)
+        err = hipStreamSynchronize(s);
+    if (err != hipSuccess)
+        return hip_fail(err, "upload tile table");
+    int bpc = 0, ncu = 0;
+    err = occupancy(p.dtype, p.nt, p.lds_bytes, &bpc);
+    if (err != hipSuccess)
+        return hip_fail(err, "occupancy query");
+    err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p.device);
+    if (err != hipSuccess)
+        return hip_fail(err, "CU count query");
+    if (bpc < 1)
+        return fail(SEM_ERR_UNSUPPORTED, "batch kernel cannot be resident with %d B of LDS",
+                    p.lds_bytes);
+    p.grid = std::max(1, std::min(p.ntiles, bpc * ncu));
+    return SEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Plan cache: a flat JSON object {"key": {"epb": E, "us": T}, ...} in the
+// file named by SEM_PLAN_CACHE, keyed by device arch, dtype, workgroup size,
+// Nq and a power-of-two element-count bucket.
+// ---------------------------------------------------------------------------
+std::mutex g_cache_mu;
+
+std::string cache_path()
+{
+    const char* p = getenv("SEM_PLAN_CACHE");
+    return p ? std::string(p) : std::string();
+}
+
+std::string arch_name(int device)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+        return "unknown";
+    std::string a = prop.gcnArchName;
+    size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string cache_key(const std::string& arch, sem_dtype dt, int nt, int nq, int64_t ne)
+{
+    int64_t bucket = 1;
+    while (bucket < ne)
+        bucket <<= 1;
+    char buf[128];
+    snprintf(buf, sizeof buf, "%s/%s/nt%d/nq%d/ne%lld", arch.c_str(), dt == SEM_F64 ? "f64" : "f32",
+             nt, nq, (long long)bucket);
+    return buf;
+}
+
+std::map<std::string, std::pair<int, double>> cache_read(const std::string& path)
+{
+    std::map<std::string, std::pair<int, double>> m;
+    FILE* f = fopen(path.c_str(), "rb");
+    if (!f)
+        return m;
+    std::string s;
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof buf, f)) > 0)
+        s.append(buf, n);
+    fclose(f);
+    size_t pos = 0;
+    while (true) {
+        size_t k0 = s.find('"', pos);
+        if (k0 == std::string::npos)
+            break;
+        size_t k1 = s.find('"', k0 + 1);
+        if (k1 == std::string::npos)
+            break;
+        std::string key = s.substr(k0 + 1, k1 - k0 - 1);
+        size_t ob = s.find('{', k1);
+        size_t cb = s.find('}', k1);
+        if (ob == std::string::npos || cb == std::string::npos || cb < ob)
+            break;
+        std::string body = s.substr(ob, cb - ob);
+        int epb = 0;
+        double us = -1.0;
+        size_t e = body.find("\"epb\"");
+        size_t u = body.find("\"us\"");
+        if (e != std::string::npos)
+            epb = atoi(body.c_str() + body.find(':', e) + 1);
+        if (u != std::string::npos)
+            us = atof(body.c_str() + body.find(':', u) + 1);
+        if (epb > 0)
+            m[key] = {epb, us};
+        pos = cb + 1;
+    }
+    return m;
+}
+
+void cache_write(const std::string& path, const std::map<std::string, std::pair<int, double>>& m)
+{
+    std::string tmp = path + ".tmp";
+    FILE* f = fopen(tmp.c_str(), "wb");
+    if (!f)
+        return;
+    fprintf(f, "{\n");
+    size_t i = 0;
+    for (const auto& kv : m) {
+        fprintf(f, "  \"%s\": {\"epb\": %d, \"us\": %.3f}%s\n", kv.first.c_str(), kv.second.first,
+                kv.second.second, ++i < m.size() ? "," : "");
+    }
+    fprintf(f, "}\n");
+    fclose(f);
+    rename(tmp.c_str(), path.c_str());
+}
+
+// Time one order's blocks alone with a candidate shape: median of 5 launches
+// after 2 warm-ups, with HIP events on the plan stream.
+sem_status time_candidate(PlanCore& p, int nq, hipStream_t s, double* us_out)
+{
+    std::vector<semh::Tile> tiles = make_tiles(p.blocks, p.orders, nq);
+    const int lds = lds_for(p.dtype, p.nt, p.orders, nq);
+    semh::Tile* d_t = nullptr;
+    hipError_t err = hipMalloc((void**)&d_t, tiles.size() * sizeof(semh::Tile));
+    if (err != hipSuccess)
+        return fail(SEM_ERR_NO_MEMORY, "autotune tile table: %s", hipGetErrorString(err));
+    err = hipMemcpy(d_t, tiles.data(), tiles.size() * sizeof(semh::Tile), hipMemcpyHostToDevice);
+    int bpc = 0, ncu = 0;
+    if (err == hipSuccess)
+        err = occupancy(p.dtype, p.nt, lds, &bpc);
+    if (err == hipSuccess)
+        err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p.device);
+    if (err != hipSuccess) {
+        (void)hipFree(d_t);
+        return hip_fail(err, "autotune setup");
+    }
+    if (bpc < 1) {
+        (void)hipFree(d_t);
+        *us_out = 1e30;
+        return SEM_OK;
+    }
+    const int grid = std::max(1, std::min((int)tiles.size(), bpc * ncu));
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    std::vector<float> ms;
+    for (int r = 0; r < 7 && err == hipSuccess; ++r) {
+        (void)hipEventRecord(e0, s);
+        err = launch(p, d_t, (int)tiles.size(), grid, lds, s);
+        (void)hipEventRecord(e1, s);
+        if (err == hipSuccess)
+            err = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (err == hipSuccess && r >= 2 && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
+            ms.push_back(t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(d_t);
+    if (err != hipSuccess)
+        return hip_fail(err, "autotune launch");
+    std::sort(ms.begin(), ms.end());
+    *us_out = ms.empty() ? 1e30 : 1e3 * ms[ms.size() / 2];
+    return SEM_OK;
+}
+
+sem_status autotune(PlanCore& p, bool use_cache, hipStream_t s)
+{
+    const std::string arch = arch_name(p.device);
+    const std::string path = use_cache ? cache_path() : std::string();
+    std::map<std::string, std::pair<int, double>> cache;
+    if (!path.empty()) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        cache = cache_read(path);
+    }
+    bool all_cached = true;
+    double best_total = 1e300;
+    int best_nt = 256;
+    std::vector<OrderChoice> best_orders;
+    // upload a block table for the timing launches
+    p.nt = 256;
+    {
+        std::vector<OrderChoice> saved = p.orders;
+        for (OrderChoice& o : p.orders)
+            o.epb = default_epb(o.nq);
+        sem_status st = finalize(p, s);
+        if (st != SEM_OK)
+            return st;
+        p.orders = saved;
+    }
+    for (int nt : semh::kBatchThreads) {
+        p.nt = nt;
+        double total = 0.0;
+        std::vector<OrderChoice> chosen = p.orders;
+        for (OrderChoice& oc : chosen) {
+            const std::string key = cache_key(arch, p.dtype, nt, oc.nq, oc.elements);
+            auto it = cache.find(key);
+            if (it != cache.end() && variant_ok(p.dtype, nt, oc.nq, it->second.first)) {
+                oc.epb = it->second.first;
+                oc.us = it->second.second;
+                total += oc.us;
+                continue;
+            }
+            all_cached = false;
+            double best = 1e300;
+            int best_epb = -1;
+            for (int i = 0; i < semh::kNumVariants; ++i) {
+                const semh::VariantDef v = semh::kVariants[i];
+                if (v.nq != oc.nq || !variant_ok(p.dtype, nt, v.nq, v.epb))
+                    continue;
+                for (OrderChoice& o : p.orders)
+                    if (o.nq == oc.nq)
+                        o.epb = v.epb;
+                double us = 0.0;
+                sem_status st = time_candidate(p, oc.nq, s, &us);
+                if (st != SEM_OK)
+                    return st;
+                if (log_enabled())
+                    fprintf(stderr, "[semvol] autotune %s nt=%d nq=%d epb=%d: %.2f us\n",
+                            p.dtype == SEM_F64 ? "f64" : "f32", nt, v.nq, v.epb, us);
+                if (us < best) {
+                    best = us;
+                    best_epb = v.epb;
+                }
+            }
+            if (best_epb < 0)
+                return fail(SEM_ERR_UNSUPPORTED, "no batch tile shape for Nq = %d", oc.nq);
+            oc.epb = best_epb;
+            oc.us = best;
+            total += best;
+            cache[key] = {best_epb, best};
+        }
+        if (total < best_total) {
+            best_total = total;
+            best_nt = nt;
+            best_orders = chosen;
+        }
+    }
+    p.nt = best_nt;
+    p.orders = best_orders;
+    p.autotuned = true;
+    p.from_cache = all_cached;
+    if (!path.empty() && !all_cached) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto merged = cache_read(path);
+        for (auto& kv : cache)
+            merged[kv.first] = kv.second;
+        cache_write(path, merged);
+    }
+    if (log_enabled())
+        fprintf(stderr, "[semvol] autotune chose nt=%d (sum of per-order times %.2f us)%s\n", p.nt,
+                best_total, all_cached ? " from cache" : "");
+    return SEM_OK;
+}
+
+sem_status build_plan(const sem_block* blocks, int32_t nblocks, sem_dtype dt, const sem_phys* phys,
+                      uint32_t flags, hipStream_t s, const PlanCore* template_plan, PlanCore** out)
+{
+    SEM_TRY(check_dtype(dt));
+    if (!out)
+        return fail(SEM_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!blocks || nblocks < 1)
+        return fail(SEM_ERR_INVALID_ARG, "need at least one block (nblocks = %d)", nblocks);
+    if (!phys)
+        return fail(SEM_ERR_INVALID_ARG, "phys is NULL");
+    for (int i = 0; i < nblocks; ++i)
+        SEM_TRY(check_block(blocks[i], i, dt, phys));
+    PlanCore* p = new (std::nothrow) PlanCore();
+    if (!p)
+        return fail(SEM_ERR_NO_MEMORY, "plan allocation");
+    p->dtype = dt;
+    p->phys = to_phys(phys);
+    p->blocks.assign(blocks, blocks + nblocks);
+    hipError_t err = hipGetDevice(&p->device);
+    if (err == hipSuccess)
+        err = dt == SEM_F64 ? semh::batch_prepare<double>() : semh::batch_prepare<float>();
+    if (err != hipSuccess) {
+        delete p;
+        return hip_fail(err, "batch kernel setup");
+    }
+    for (int i = 0; i < nblocks; ++i) {
+        bool found = false;
+        for (OrderChoice& o : p->orders)
+            if (o.nq == blocks[i].Nq) {
+                o.elements += blocks[i].Ne;
+                found = true;
+            }
+        if (!found) {
+            OrderChoice o;
+            o.nq = blocks[i].Nq;
+            o.epb = default_epb(o.nq);
+            o.elements = blocks[i].Ne;
+            p->orders.push_back(o);
+        }
+    }
+    std::sort(p->orders.begin(), p->orders.end(),
+              [](const OrderChoice& a, const OrderChoice& b) { return a.nq < b.nq; });
+    sem_status st = SEM_OK;
+    if (template_plan) {
+        p->nt = template_plan->nt;
+        p->orders = template_plan->orders;
+        p->autotuned = template_plan->autotuned;
+        p->from_cache = template_plan->from_cache;
+    } else if (flags & SEM_PLAN_AUTOTUNE) {
+        st = autotune(*p, (flags & SEM_PLAN_USE_CACHE) != 0, s);
+    } else {
+        p->nt = 256;
+        for (OrderChoice& o : p->orders)
+            if (!variant_ok(dt, p->nt, o.nq, o.epb))
+                st = fail(SEM_ERR_UNSUPPORTED, "no default batch shape for Nq = %d", o.nq);
+    }
+    if (st == SEM_OK)
+        st = finalize(*p, s);
+    if (st != SEM_OK) {
+        free_core(p);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return SEM_OK;
+}
+
+}  // namespace
+
+struct sem_plan_s {
+    PlanCore core;
+};
+
+extern "C" sem_status sem_batch_plan(const sem_block* blocks, int32_t nblocks, sem_dtype dtype,
+                                     const sem_phys* phys, uint32_t flags, void* stream,
+                                     sem_plan* out)
+{
+    if (!out)
+        return fail(SEM_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    PlanCore* core = nullptr;
+    SEM_TRY(build_plan(blocks, nblocks, dtype, phys, flags, static_cast<hipStream_t>(stream), nullptr,
+                       &core));
+    sem_plan p = new (std::nothrow) sem_plan_s();
+    if (!p) {
+        free_core(core);
+        delete core;
+        return fail(SEM_ERR_NO_MEMORY, "plan allocation");
+    }
+    p->core = *core;   // takes over the device tables
+    delete core;
+    *out = p;
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_batch_execute(sem_plan plan, void* stream)
+{
+    if (!plan)
+        return fail(SEM_ERR_INVALID_ARG, "plan is NULL");
+    const PlanCore& c = plan->core;
+    if (!c.d_tiles || !c.d_blocks)
+        return fail(SEM_ERR_INVALID_ARG, "plan has no device tables (destroyed?)");
+    hipError_t err = launch(c, c.d_tiles, c.ntiles, c.grid, c.lds_bytes,
+                            static_cast<hipStream_t>(stream));
+    if (err != hipSuccess)
+        return hip_fail(err, "batch kernel launch");
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_plan_describe(sem_plan plan, char* buf, int32_t len)
+{
+    if (!plan || !buf || len < 1)
+        return fail(SEM_ERR_INVALID_ARG, "NULL plan or buffer");
+    const PlanCore& c = plan->core;
+    std::string s = "{\"dtype\": \"";
+    s += c.dtype == SEM_F64 ? "f64" : "f32";
+    char tmp[256];
+    snprintf(tmp, sizeof tmp,
+             "\", \"threads\": %d, \"grid\": %d, \"lds_bytes\": %d, \"tiles\": %d, "
+             "\"blocks\": %zu, \"autotuned\": %s, \"from_cache\": %s, \"orders\": [",
+             c.nt, c.grid, c.lds_bytes, c.ntiles, c.blocks.size(), c.autotuned ? "true" : "false",
+             c.from_cache ? "true" : "false");
+    s += tmp;
+    for (size_t i = 0; i < c.orders.size(); ++i) {
+        snprintf(tmp, sizeof tmp, "%s{\"Nq\": %d, \"elems_per_block\": %d, \"elements\": %lld, "
+                                  "\"tuned_us\": %.3f}",
+                 i ? ", " : "", c.orders[i].nq, c.orders[i].epb, (long long)c.orders[i].elements,
+                 c.orders[i].us);
+        s += tmp;
+    }
+    s += "]}";
+    snprintf(buf, (size_t)len, "%s", s.c_str());
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_plan_destroy(sem_plan plan)
+{
+    if (!plan)
+        return fail(SEM_ERR_INVALID_ARG, "plan is NULL");
+    free_core(&plan->core);
+    delete plan;
+    return SEM_OK;
+}
+
+// ===========================================================================
+// SSP-RK3 step in a HIP graph
+// ===========================================================================
+struct sem_rk3_s {
+    PlanCore stage[3];
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" sem_status sem_rk3_graph_create(const sem_block* blocks, int32_t nblocks, sem_dtype dtype,
+                                           const sem_phys* phys, uint32_t flags, void* q_n,
+                                           void* q_1, void* q_2, void* L, int64_t n, double dt,
+                                           void* stream, sem_rk3* out)
+{
+    if (!out)
+        return fail(SEM_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    SEM_TRY(check_dtype(dtype));
+    const size_t es = elem_size(dtype);
+    SEM_TRY(check_ptr(q_n, es, "q_n"));
+    SEM_TRY(check_ptr(q_1, es, "q_1"));
+    SEM_TRY(check_ptr(q_2, es, "q_2"));
+    SEM_TRY(check_ptr(L, es, "L"));
+    if (n < 1)
+        return fail(SEM_ERR_INVALID_ARG, "n = %lld < 1", (long long)n);
+    if (!blocks || nblocks < 1)
+        return fail(SEM_ERR_INVALID_ARG, "need at least one block");
+    if (!std::isfinite(dt))
+        return fail(SEM_ERR_INVALID_ARG, "dt is not finite");
+    // every block's q inside q_n and its rhs inside L at the same offset
+    std::vector<sem_block> b1(blocks, blocks + nblocks), b2(blocks, blocks + nblocks);
+    const char* qn = static_cast<const char*>(q_n);
+    const char* lb = static_cast<const char*>(L);
+    for (int i = 0; i < nblocks; ++i) {
+        const int64_t m = (int64_t)blocks[i].Nq * blocks[i].Nq * blocks[i].Nq;
+        const int64_t bytes = (int64_t)blocks[i].Ne * 5 * m * (int64_t)es;
+        const int64_t off = static_cast<const char*>(blocks[i].q) - qn;
+        const int64_t roff = static_cast<const char*>((const void*)blocks[i].rhs) - lb;
+        if (off < 0 || off + bytes > n * (int64_t)es)
+            return fail(SEM_ERR_INVALID_ARG, "block %d: q is not inside q_n[0, n)", i);
+        if (roff != off)
+            return fail(SEM_ERR_INVALID_ARG, "block %d: rhs is not at the same offset in L as q in q_n",
+                        i);
+        b1[i].q = static_cast<const char*>(q_1) + off;
+        b2[i].q = static_cast<const char*>(q_2) + off;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    sem_rk3 g = new (std::nothrow) sem_rk3_s();
+    if (!g)
+        return fail(SEM_ERR_NO_MEMORY, "graph allocation");
+    PlanCore* c0 = nullptr;
+    PlanCore* c1 = nullptr;
+    PlanCore* c2 = nullptr;
+    sem_status st = build_plan(blocks, nblocks, dtype, phys, flags, s, nullptr, &c0);
+    if (st == SEM_OK)
+        st = build_plan(b1.data(), nblocks, dtype, phys, 0, s, c0, &c1);
+    if (st == SEM_OK)
+        st = build_plan(b2.data(), nblocks, dtype, phys, 0, s, c0, &c2);
+    auto cleanup = [&]() {
+        for (PlanCore* c : {c0, c1, c2})
+            if (c) {
+                free_core(c);
+                delete c;
+            }
+    };
+    if (st != SEM_OK) {
+        cleanup();
+        delete g;
+        return st;
+    }
+    g->stage[0] = *c0;
+    g->stage[1] = *c1;
+    g->stage[2] = *c2;
+    delete c0;
+    delete c1;
+    delete c2;
+    auto destroy_all = [&]() {
+        for (PlanCore& c : g->stage)
+            free_core(&c);
+        if (g->exec)
+            (void)hipGraphExecDestroy(g->exec);
+        if (g->graph)
+            (void)hipGraphDestroy(g->graph);
+        delete g;
+    };
+    // Shu-Osher coefficients: stage s writes a_s q_n + b_s (q_s + dt L)
+    const double a[3] = {0.0, 0.75, 1.0 / 3.0};
+    const double b[3] = {1.0, 0.25, 2.0 / 3.0};
+    void* qin[3] = {q_n, q_1, q_2};
+    void* qout[3] = {q_1, q_2, q_n};
+    hipStream_t cs = nullptr;
+    hipError_t err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (err != hipSuccess) {
+        destroy_all();
+        return hip_fail(err, "capture stream");
+    }
+    err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    for (int k = 0; k < 3 && err == hipSuccess; ++k) {
+        const PlanCore& c = g->stage[k];
+        err = launch(c, c.d_tiles, c.ntiles, c.grid, c.lds_bytes, cs);
+        if (err == hipSuccess) {
+            if (dtype == SEM_F64)
+                err = semh::launch_axpby<double>(n, a[k], static_cast<const double*>(q_n), b[k],
+                                                 static_cast<const double*>(qin[k]), dt,
+                                                 static_cast<const double*>(L),
+                                                 static_cast<double*>(qout[k]), cs);
+            else
+                err = semh::launch_axpby<float>(n, a[k], static_cast<const float*>(q_n), b[k],
+                                                static_cast<const float*>(qin[k]), dt,
+                                                static_cast<const float*>(L),
+                                                static_cast<float*>(qout[k]), cs);
+        }
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t err_end = hipStreamEndCapture(cs, &graph);
+    if (err == hipSuccess)
+        err = err_end;
+    g->graph = graph;
+    if (err == hipSuccess)
+        err = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (err != hipSuccess) {
+        destroy_all();
+        return hip_fail(err, "RK3 graph capture");
+    }
+    *out = g;
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_rk3_graph_launch(sem_rk3 step, void* stream)
+{
+    if (!step || !step->exec)
+        return fail(SEM_ERR_INVALID_ARG, "step is NULL or destroyed");
+    hipError_t err = hipGraphLaunch(step->exec, static_cast<hipStream_t>(stream));
+    if (err != hipSuccess)
+        return hip_fail(err, "hipGraphLaunch");
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_rk3_graph_destroy(sem_rk3 step)
+{
+    if (!step)
+        return fail(SEM_ERR_INVALID_ARG, "step is NULL");
+    for (PlanCore& c : step->stage)
+        free_core(&c);
+    if (step->exec)
+        (void)hipGraphExecDestroy(step->exec);
+    if (step->graph)
+        (void)hipGraphDestroy(step->graph);
+    delete step;
+    return SEM_OK;
+}

@@ -1,0 +1,413 @@
+// Device-side building blocks of the strong-form volume term (Sec. 2,
+// Eq. (volterm)) for gfx950.  Everything here is internal to libsem.so.
+//
+// Layouts (element outermost, structure-of-arrays inside an element):
+//   q, rhs, lambda, mu : [Ne][5][Nq^3]   fields rho, U1, U2, U3, Theta
+//   geo                : [Ne][10][Nq^3]  slot 3*d + a = g_{a d}, slot 9 = 1/J
+//   rho_ref            : [Ne][Nq^3]      (same dtype as q)
+//   theta_ref          : [Ne][Nq^3]      always FP64
+//   D                  : [Nq][Nq]        D[i*Nq + n] = l_n'(xi_i)
+//   node m = i + Nq*j + Nq^2*k, with i, j, k along r, s, t (Fig. 1).
+//
+// One workgroup owns a tile of EPB whole elements.  Every thread handles
+// the nodes tid, tid + NT, ... of the tile.  Phase 1 reads each node's state
+// and metric terms once, evaluates the pressure and the contravariant fluxes
+// of all three reference directions and stages them in LDS (the paper's
+// flux precompute and state prefetch); phase 2 applies D along r, s and t
+// out of LDS, accumulates in registers, applies 1/J once (distributive
+// law), adds the gravity source and writes each output once.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace semk {
+
+struct Phys {
+    double p0, gamma, R, grav;
+    double r_over_p0;   // R / p0, formed once on the host
+};
+
+template <typename T>
+struct BlockPtrs {
+    const T* D;
+    const T* geo;
+    const T* q;
+    const T* rho_ref;        // nullable (then rho_ref = 0)
+    const double* theta_ref; // nullable (then the full pressure is used)
+    T* rhs;
+    int64_t Ne;
+};
+
+// ---------------------------------------------------------------------------
+// Pressure entering the flux (Sec. 2 EOS p = p0 (R Theta / p0)^gamma).
+// With a reference state it is the perturbation p - p_ref.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Pressure;
+
+template <>
+struct Pressure<double> {
+    // FP64: both powers through the library pow, differenced before the
+    // scaling by p0, so that Theta == Theta_ref gives exactly zero (a fused
+    // p0*a - p0*b would keep the rounding error of one product).
+    static __device__ __forceinline__ double eval(double Th, bool has_ref, double thr,
+                                                  const Phys& ph)
+    {
+        const double s = ph.r_over_p0;
+        double x = pow(s * Th, ph.gamma);
+        if (has_ref)
+            x -= pow(s * thr, ph.gamma);
+        return ph.p0 * x;
+    }
+    // dp/dTheta = gamma p / Theta (full pressure, for the adjoint)
+    static __device__ __forceinline__ double dp_dtheta(double Th, const Phys& ph)
+    {
+        const double p = ph.p0 * pow(ph.r_over_p0 * Th, ph.gamma);
+        return ph.gamma * p / Th;
+    }
+};
+
+template <>
+struct Pressure<float> {
+    // FP32 perturbation form: Theta' = Theta - Theta_ref is formed in FP64
+    // (Theta_ref is stored in FP64), then
+    //   p' = p_ref * expm1(gamma * log1p(Theta'/Theta_ref)),
+    // which uses EOS(Theta)/EOS(Theta_ref) = (Theta/Theta_ref)^gamma and keeps
+    // the relative accuracy of the small perturbation instead of cancelling
+    // two large FP32 pressures.
+    static __device__ __forceinline__ float eval(float Th, bool has_ref, double thr,
+                                                 const Phys& ph)
+    {
+        const float p0 = (float)ph.p0, g = (float)ph.gamma, s = (float)ph.r_over_p0;
+        if (has_ref) {
+            const float dth = (float)((double)Th - thr);
+            const float trf = (float)thr;
+            const float pref = p0 * powf(s * trf, g);
+            return pref * expm1f(g * log1pf(dth / trf));
+        }
+        return p0 * powf(s * Th, g);
+    }
+    static __device__ __forceinline__ float dp_dtheta(float Th, const Phys& ph)
+    {
+        const float p0 = (float)ph.p0, g = (float)ph.gamma, s = (float)ph.r_over_p0;
+        return g * (p0 * powf(s * Th, g)) / Th;
+    }
+};
+
+template <int NQ>
+struct Shape {
+    static constexpr int NQ2 = NQ * NQ;
+    static constexpr int M = NQ * NQ * NQ;
+    // D is staged in front of the flux area; pad it to 16 bytes
+    template <typename T>
+    static constexpr int d_slots()
+    {
+        return ((NQ2 * (int)sizeof(T) + 15) / 16) * 16 / (int)sizeof(T);
+    }
+};
+
+// A thread that handles more than one node of a tile keeps 1/J and the
+// gravity source of its nodes in LDS (two extra values per node) instead of
+// register arrays, so that its node loop need not be unrolled.
+template <typename T, int NQ, int EPB, int NT>
+constexpr int volume_tile_values_per_node()
+{
+    return (EPB * Shape<NQ>::M + NT - 1) / NT > 1 ? 17 : 15;
+}
+
+// LDS bytes a forward tile needs: D plus the staged values of every node.
+template <typename T, int NQ, int EPB, int NT>
+constexpr int volume_tile_lds_bytes()
+{
+    return (Shape<NQ>::template d_slots<T>() +
+            EPB * volume_tile_values_per_node<T, NQ, EPB, NT>() * Shape<NQ>::M) *
+           (int)sizeof(T);
+}
+
+// ---------------------------------------------------------------------------
+// Forward tile: EPB elements starting at e0, of which the first ne exist.
+// ---------------------------------------------------------------------------
+template <typename T, int NQ, int EPB, int NT>
+__device__ __forceinline__ void volume_tile(const BlockPtrs<T>& B, int64_t e0, int ne,
+                                            const Phys& ph, int accumulate, T* __restrict__ smem)
+{
+    constexpr int NQ2 = Shape<NQ>::NQ2;
+    constexpr int M = Shape<NQ>::M;
+    constexpr int NODES = EPB * M;
+    constexpr int NPT = (NODES + NT - 1) / NT;
+    constexpr int VPN = volume_tile_values_per_node<T, NQ, EPB, NT>();
+    T* __restrict__ sD = smem;
+    T* __restrict__ sF = smem + Shape<NQ>::template d_slots<T>();
+    const int tid = threadIdx.x;
+
+    for (int x = tid; x < NQ2; x += NT)
+        sD[x] = B.D[x];
+
+    const bool has_ref = B.theta_ref != nullptr;
+    const T grav = (T)ph.grav;
+
+    // Phase 1 for tile node t: pointwise pressure and contravariant fluxes
+    // of the three directions into LDS; returns 1/J and the source.
+    auto phase1 = [&](int t, T& jinv, T& src) {
+        const int es = t / M;
+        const int m = t - es * M;
+        const int64_t e = e0 + es;
+        const T* __restrict__ qe = B.q + e * (5 * M) + m;
+        const T* __restrict__ ge = B.geo + e * (10 * M) + m;
+        const T rho = qe[0], U1 = qe[M], U2 = qe[2 * M], U3 = qe[3 * M], Th = qe[4 * M];
+        T g[9];
+#pragma unroll
+        for (int s = 0; s < 9; ++s)
+            g[s] = ge[s * M];
+        jinv = ge[9 * M];
+        T rr = (T)0;
+        double thr = 0.0;
+        if (has_ref) {
+            rr = B.rho_ref[e * M + m];
+            thr = B.theta_ref[e * M + m];
+        }
+        src = -grav * (rho - rr);
+        const T pp = Pressure<T>::eval(Th, has_ref, thr, ph);
+        const T rinv = (T)1 / rho;
+        T* __restrict__ F = sF + es * (VPN * M) + m;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const T g1 = g[3 * d], g2 = g[3 * d + 1], g3 = g[3 * d + 2];
+            const T Ud = g1 * U1 + g2 * U2 + g3 * U3;   // contravariant momentum
+            const T vd = Ud * rinv;
+            T* Fd = F + d * (5 * M);
+            Fd[0] = Ud;
+            Fd[M] = U1 * vd + g1 * pp;
+            Fd[2 * M] = U2 * vd + g2 * pp;
+            Fd[3 * M] = U3 * vd + g3 * pp;
+            Fd[4 * M] = Th * vd;
+        }
+    };
+
+    // Phase 2 for tile node t: D along r, s, t out of LDS, then
+    // rhs = -(1/J) * sum + source, written once.
+    auto phase2 = [&](int t, T jinv, T src) {
+        const int es = t / M;
+        const int m = t - es * M;
+        const int i = m % NQ;
+        const int j = (m / NQ) % NQ;
+        const int k = m / NQ2;
+        const T* __restrict__ Fe = sF + es * (VPN * M);
+        T acc[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
+        {   // r: sum_n D[i][n] F^r(n, j, k)
+            const T* Fr = Fe + NQ * j + NQ2 * k;
+#pragma unroll 2
+            for (int n = 0; n < NQ; ++n) {
+                const T dn = sD[i * NQ + n];
+#pragma unroll
+                for (int b = 0; b < 5; ++b)
+                    acc[b] += dn * Fr[b * M + n];
+            }
+        }
+        {   // s: sum_n D[j][n] F^s(i, n, k)
+            const T* Fs = Fe + 5 * M + i + NQ2 * k;
+#pragma unroll 2
+            for (int n = 0; n < NQ; ++n) {
+                const T dn = sD[j * NQ + n];
+#pragma unroll
+                for (int b = 0; b < 5; ++b)
+                    acc[b] += dn * Fs[b * M + NQ * n];
+            }
+        }
+        {   // t: sum_n D[k][n] F^t(i, j, n)
+            const T* Ft = Fe + 10 * M + i + NQ * j;
+#pragma unroll 2
+            for (int n = 0; n < NQ; ++n) {
+                const T dn = sD[k * NQ + n];
+#pragma unroll
+                for (int b = 0; b < 5; ++b)
+                    acc[b] += dn * Ft[b * M + NQ2 * n];
+            }
+        }
+        const int64_t e = e0 + es;
+        T* __restrict__ re = B.rhs + e * (5 * M) + m;
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+            T v = -jinv * acc[b];
+            if (b == 3)
+                v += src;
+            if (accumulate)
+                v += re[b * M];
+            re[b * M] = v;
+        }
+    };
+
+    if constexpr (NPT == 1) {
+        const bool live = tid < NODES && tid / M < ne;
+        T jinv = (T)0, src = (T)0;
+        if (live)
+            phase1(tid, jinv, src);
+        __syncthreads();
+        if (live)
+            phase2(tid, jinv, src);
+    } else {
+#pragma unroll 1
+        for (int t = tid; t < NODES; t += NT) {
+            if (t / M < ne) {
+                T jinv, src;
+                phase1(t, jinv, src);
+                const int es = t / M;
+                T* S = sF + es * (VPN * M) + 15 * M + (t - es * M);
+                S[0] = jinv;
+                S[M] = src;
+            }
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int t = tid; t < NODES; t += NT) {
+            if (t / M < ne) {
+                const int es = t / M;
+                const T* S = sF + es * (VPN * M) + 15 * M + (t - es * M);
+                phase2(t, S[0], S[M]);
+            }
+        }
+    }
+    __syncthreads();   // the LDS tile is reused by the next tile of a persistent workgroup
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint tile (vector-Jacobian product with respect to q).
+//   w_b(x)   = -(1/J(x)) lambda_b(x)                       (phase 1, to LDS)
+//   G^d_b(y) = sum_x Dd[x][y] w_b(x)   along r, s, t       (phase 2, D^T)
+//   with v^d = U^d/rho and A^d = sum_a G^d_{Ua} U_a + G^d_Theta Theta:
+//   mu_rho = -(1/rho) sum_d v^d A^d - grav lambda_U3
+//   mu_Uc  = sum_d [ g_cd (G^d_rho + A^d/rho) + v^d G^d_Uc ]
+//   mu_Th  = sum_d [ (dp/dTheta) sum_a g_ad G^d_Ua + v^d G^d_Theta ]
+// ---------------------------------------------------------------------------
+template <typename T>
+struct AdjPtrs {
+    const T* D;
+    const T* geo;
+    const T* q;
+    const T* lambda;
+    T* mu;
+    int64_t Ne;
+};
+
+template <typename T, int NQ, int EPB, int NT>
+__device__ __forceinline__ void adjoint_tile(const AdjPtrs<T>& B, int64_t e0, int ne,
+                                             const Phys& ph, int accumulate, T* __restrict__ smem)
+{
+    constexpr int NQ2 = Shape<NQ>::NQ2;
+    constexpr int M = Shape<NQ>::M;
+    constexpr int NODES = EPB * M;
+    constexpr int NPT = (NODES + NT - 1) / NT;
+    T* __restrict__ sD = smem;
+    T* __restrict__ sW = smem + Shape<NQ>::template d_slots<T>();
+    const int tid = threadIdx.x;
+
+    for (int x = tid; x < NQ2; x += NT)
+        sD[x] = B.D[x];
+
+    T lam3[NPT];
+#pragma unroll
+    for (int p = 0; p < NPT; ++p) {
+        const int t = tid + p * NT;
+        const int es = t / M;
+        const int m = t - es * M;
+        if (t < NODES && es < ne) {
+            const int64_t e = e0 + es;
+            const T* __restrict__ le = B.lambda + e * (5 * M) + m;
+            const T jinv = B.geo[e * (10 * M) + 9 * M + m];
+            T* W = sW + es * (5 * M) + m;
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+                const T lb = le[b * M];
+                if (b == 3)
+                    lam3[p] = lb;
+                W[b * M] = -jinv * lb;
+            }
+        }
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int p = 0; p < NPT; ++p) {
+        const int t = tid + p * NT;
+        const int es = t / M;
+        const int m = t - es * M;
+        if (t < NODES && es < ne) {
+            const int i = m % NQ;
+            const int j = (m / NQ) % NQ;
+            const int k = m / NQ2;
+            const int64_t e = e0 + es;
+            const T* __restrict__ qe = B.q + e * (5 * M) + m;
+            const T* __restrict__ ge = B.geo + e * (10 * M) + m;
+            const T rho = qe[0], U1 = qe[M], U2 = qe[2 * M], U3 = qe[3 * M], Th = qe[4 * M];
+            T g[9];
+#pragma unroll
+            for (int s = 0; s < 9; ++s)
+                g[s] = ge[s * M];
+            const T* __restrict__ We = sW + es * (5 * M);
+            T G[3][5];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int b = 0; b < 5; ++b)
+                    G[d][b] = (T)0;
+            {   // r: G^r(i,j,k) = sum_x D[x][i] w(x, j, k)
+                const T* Wr = We + NQ * j + NQ2 * k;
+#pragma unroll 2
+                for (int x = 0; x < NQ; ++x) {
+                    const T dx = sD[x * NQ + i];
+#pragma unroll
+                    for (int b = 0; b < 5; ++b)
+                        G[0][b] += dx * Wr[b * M + x];
+                }
+            }
+            {   // s: G^s(i,j,k) = sum_x D[x][j] w(i, x, k)
+                const T* Ws = We + i + NQ2 * k;
+#pragma unroll 2
+                for (int x = 0; x < NQ; ++x) {
+                    const T dx = sD[x * NQ + j];
+#pragma unroll
+                    for (int b = 0; b < 5; ++b)
+                        G[1][b] += dx * Ws[b * M + NQ * x];
+                }
+            }
+            {   // t: G^t(i,j,k) = sum_x D[x][k] w(i, j, x)
+                const T* Wt = We + i + NQ * j;
+#pragma unroll 2
+                for (int x = 0; x < NQ; ++x) {
+                    const T dx = sD[x * NQ + k];
+#pragma unroll
+                    for (int b = 0; b < 5; ++b)
+                        G[2][b] += dx * Wt[b * M + NQ2 * x];
+                }
+            }
+            const T rinv = (T)1 / rho;
+            const T dpdT = Pressure<T>::dp_dtheta(Th, ph);
+            T mu0 = (T)0, mu1 = (T)0, mu2 = (T)0, mu3 = (T)0, mu4 = (T)0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const T g1 = g[3 * d], g2 = g[3 * d + 1], g3 = g[3 * d + 2];
+                const T vd = (g1 * U1 + g2 * U2 + g3 * U3) * rinv;
+                const T Ad = G[d][1] * U1 + G[d][2] * U2 + G[d][3] * U3 + G[d][4] * Th;
+                const T cd = G[d][0] + Ad * rinv;
+                mu0 += vd * Ad;
+                mu1 += g1 * cd + vd * G[d][1];
+                mu2 += g2 * cd + vd * G[d][2];
+                mu3 += g3 * cd + vd * G[d][3];
+                mu4 += dpdT * (g1 * G[d][1] + g2 * G[d][2] + g3 * G[d][3]) + vd * G[d][4];
+            }
+            mu0 = -rinv * mu0 - (T)ph.grav * lam3[p];
+            T* __restrict__ me = B.mu + e * (5 * M) + m;
+            const T out[5] = {mu0, mu1, mu2, mu3, mu4};
+#pragma unroll
+            for (int b = 0; b < 5; ++b) {
+                T v = out[b];
+                if (accumulate)
+                    v += me[b * M];
+                me[b * M] = v;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+}  // namespace semk

@@ -1,0 +1,77 @@
+// Internal host-side interface between the C-ABI layer (sem_api.cpp) and the
+// kernel translation units.  Not installed; not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sem_device.hpp"
+
+// Compiled tile shapes (Nq, elements per workgroup).  The single-order
+// kernels use ceil64(EPB * Nq^3) threads (one node per thread); the
+// persistent batch kernel runs every shape with a fixed workgroup size.
+#define SEM_VARIANTS(X)                                   \
+    X(2, 8) X(2, 16) X(2, 32) X(2, 64) X(2, 128)          \
+    X(3, 4) X(3, 8) X(3, 16) X(3, 32)                     \
+    X(4, 1) X(4, 2) X(4, 4) X(4, 8) X(4, 16)              \
+    X(5, 1) X(5, 2) X(5, 4) X(5, 8)                       \
+    X(6, 1) X(6, 2) X(6, 4)                               \
+    X(7, 1) X(7, 2)                                       \
+    X(8, 1) X(8, 2)                                       \
+    X(9, 1)                                               \
+    X(10, 1)
+
+namespace semh {
+
+struct VariantDef {
+    int nq, epb;
+};
+#define SEM_X_DEF(NQ_, EPB_) VariantDef{NQ_, EPB_},
+inline constexpr VariantDef kVariants[] = {SEM_VARIANTS(SEM_X_DEF)};
+#undef SEM_X_DEF
+inline constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
+
+constexpr int variant_index(int nq, int epb)
+{
+    for (int i = 0; i < kNumVariants; ++i)
+        if (kVariants[i].nq == nq && kVariants[i].epb == epb)
+            return i;
+    return -1;
+}
+
+constexpr int kMaxLdsBytes = 160 * 1024;   // LDS per CU on gfx950
+constexpr int kBatchThreads[] = {256, 512};
+
+// Single-order forward/adjoint launchers (defined per dtype in kernels_*.hip).
+template <typename T>
+hipError_t launch_volume(int nq, int epb, const semk::BlockPtrs<T>& B, const semk::Phys& ph,
+                         int accumulate, hipStream_t s);
+template <typename T>
+hipError_t launch_adjoint(int nq, int epb, const semk::AdjPtrs<T>& B, const semk::Phys& ph,
+                          int accumulate, hipStream_t s);
+template <typename T>
+hipError_t launch_axpby(int64_t n, double a, const T* x, double b, const T* y, double c,
+                        const T* z, T* out, hipStream_t s);
+
+// Persistent batch kernel (defined per dtype in batch_*.hip).
+struct Tile {
+    int32_t block;
+    int32_t variant;
+    int32_t ne;
+    int32_t pad;
+    int64_t e0;
+};
+template <typename T>
+bool batch_variant_ok(int nt, int nq, int epb);
+template <typename T>
+int batch_lds_bytes(int nt, int nq, int epb);
+template <typename T>
+hipError_t launch_batch(int nt, const Tile* d_tiles, int ntiles, const semk::BlockPtrs<T>* d_blocks,
+                        const semk::Phys& ph, int grid, int lds_bytes, hipStream_t s);
+template <typename T>
+hipError_t batch_blocks_per_cu(int nt, int lds_bytes, int* out);
+// Must run once per process before occupancy queries or launches (sets the
+// dynamic-LDS limit of the batch kernels).
+template <typename T>
+hipError_t batch_prepare();
+
+}  // namespace semh

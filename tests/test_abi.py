@@ -1,0 +1,151 @@
+"""CPU checks of the C-ABI: libsem.so loads, exports every function that
+include/sem.h declares, and rejects invalid arguments on the host before any
+HIP call (every call below fails validation, so no kernel is launched and no
+device memory is touched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sem.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1604_08501_amd import semvol
+    if not os.path.exists(semvol.LIB_PATH):
+        from paper_1604_08501_amd import build
+        build.build()
+    return semvol.lib()
+
+
+@pytest.fixture(scope="module")
+def sv():
+    from paper_1604_08501_amd import semvol
+    return semvol
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sem_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L, sv):
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(sv.EXPORTS)
+
+
+def test_version(L):
+    assert b"gfx950" in L.sem_version()
+
+
+def test_tile_options(L, sv):
+    buf = (ctypes.c_int32 * 16)()
+    for nq in range(2, 11):
+        n = L.sem_tile_options(sv.SEM_F64, nq, buf, 16)
+        assert n >= 1
+        assert all(buf[i] >= 1 for i in range(n))
+    assert L.sem_tile_options(sv.SEM_F64, 11, buf, 16) == 0
+    assert L.sem_tile_options(7, 8, buf, 16) == 0
+
+
+# fake, suitably aligned device addresses: validation must fail before use
+A = 0x10000
+
+
+def _vol(L, sv, Ne=4, Nq=5, dt=0, D=A, geo=2 * A, q=3 * A, rr=None, tr=None, rhs=4 * A,
+         phys=True, acc=0):
+    ph = sv.sem_phys(1e5, 1.4, 287.0, 9.81)
+    return L.sem_volume_rhs(Ne, Nq, dt, D, geo, q, rr, tr, ctypes.byref(ph) if phys else None,
+                            rhs, acc, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(Ne=0), -1), (dict(Ne=-3), -1),
+    (dict(Nq=1), -2), (dict(Nq=11), -2),
+    (dict(dt=5), -1),
+    (dict(D=None), -1), (dict(geo=None), -1), (dict(q=None), -1), (dict(rhs=None), -1),
+    (dict(rr=5 * A), -1), (dict(tr=5 * A), -1),
+    (dict(q=3 * A + 4), -1), (dict(dt=1, q=3 * A + 2), -1), (dict(rr=5 * A, tr=6 * A + 4), -1),
+    (dict(rhs=3 * A), -1),
+    (dict(phys=False), -1),
+])
+def test_volume_rhs_validation(L, sv, kw, status):
+    assert _vol(L, sv, **kw) == status
+    assert len(L.sem_last_error()) > 0
+
+
+def test_tiled_rejects_uncompiled_shape(L, sv):
+    ph = sv.sem_phys(1e5, 1.4, 287.0, 9.81)
+    tile = sv.sem_tile(3, 0)
+    st = L.sem_volume_rhs_tiled(4, 8, 0, A, 2 * A, 3 * A, None, None, ctypes.byref(ph), 4 * A, 0,
+                                ctypes.byref(tile), None)
+    assert st == sv.SEM_ERR_UNSUPPORTED
+    assert b"elems_per_block" in L.sem_last_error()
+
+
+def test_adjoint_validation(L, sv):
+    ph = sv.sem_phys(1e5, 1.4, 287.0, 9.81)
+    assert L.sem_volume_rhs_adjoint(0, 8, 0, A, 2 * A, 3 * A, ctypes.byref(ph), 4 * A, 5 * A, 0,
+                                    None) == -1
+    assert L.sem_volume_rhs_adjoint(4, 8, 0, A, 2 * A, 3 * A, ctypes.byref(ph), None, 5 * A, 0,
+                                    None) == -1
+    assert L.sem_volume_rhs_adjoint(4, 8, 0, A, 2 * A, 3 * A, ctypes.byref(ph), 4 * A, 4 * A, 0,
+                                    None) == -1
+    assert L.sem_volume_rhs_adjoint(4, 12, 0, A, 2 * A, 3 * A, ctypes.byref(ph), 4 * A, 5 * A, 0,
+                                    None) == -2
+
+
+def test_axpby_validation(L, sv):
+    assert L.sem_axpby(-1, 0, 1.0, A, 1.0, A, 1.0, A, A, None) == -1
+    assert L.sem_axpby(10, 0, 1.0, None, 1.0, A, 1.0, A, A, None) == -1   # x needed when a != 0
+    assert L.sem_axpby(10, 3, 1.0, A, 1.0, A, 1.0, A, A, None) == -1
+    assert L.sem_axpby(10, 0, 0.0, None, 1.0, A + 1, 1.0, A, A, None) == -1
+
+
+def test_batch_plan_validation(L, sv):
+    ph = sv.sem_phys(1e5, 1.4, 287.0, 9.81)
+    out = ctypes.c_void_p()
+    blocks = (sv.sem_block * 2)()
+    blocks[0] = sv.sem_block(5, 10, A, 2 * A, 3 * A, None, None, 4 * A)
+    blocks[1] = sv.sem_block(13, 10, A, 2 * A, 3 * A, None, None, 4 * A)     # Nq not compiled
+    assert L.sem_batch_plan(blocks, 0, 0, ctypes.byref(ph), 0, None, ctypes.byref(out)) == -1
+    assert L.sem_batch_plan(blocks, 2, 0, ctypes.byref(ph), 0, None, ctypes.byref(out)) == -2
+    assert b"block 1" in L.sem_last_error()
+    assert not out.value
+    assert L.sem_batch_execute(None, None) == -1
+    assert L.sem_plan_destroy(None) == -1
+    buf = ctypes.create_string_buffer(16)
+    assert L.sem_plan_describe(None, buf, 16) == -1
+
+
+def test_rk3_validation(L, sv):
+    ph = sv.sem_phys(1e5, 1.4, 287.0, 9.81)
+    out = ctypes.c_void_p()
+    blocks = (sv.sem_block * 1)()
+    M = 5 ** 3
+    blocks[0] = sv.sem_block(5, 2, A, 2 * A, 3 * A, None, None, 4 * A)
+    # q not inside q_n
+    assert L.sem_rk3_graph_create(blocks, 1, 0, ctypes.byref(ph), 0, 8 * A, 9 * A, 10 * A, 4 * A,
+                                  2 * 5 * M, 1e-3, None, ctypes.byref(out)) == -1
+    # rhs not at the same offset in L as q in q_n
+    assert L.sem_rk3_graph_create(blocks, 1, 0, ctypes.byref(ph), 0, 3 * A, 9 * A, 10 * A,
+                                  4 * A - 8, 2 * 5 * M, 1e-3, None, ctypes.byref(out)) == -1
+    assert L.sem_rk3_graph_create(blocks, 1, 0, ctypes.byref(ph), 0, 3 * A, 9 * A, 10 * A, 4 * A,
+                                  0, 1e-3, None, ctypes.byref(out)) == -1
+    assert L.sem_rk3_graph_launch(None, None) == -1
+    assert L.sem_rk3_graph_destroy(None) == -1
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    from paper_1604_08501_amd import semvol
+    monkeypatch.setattr(semvol, "_lib", None)
+    monkeypatch.setattr(semvol, "LIB_PATH", "/nonexistent/libsem.so")
+    with pytest.raises(ImportError):
+        semvol.lib()
