@@ -103,6 +103,11 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
+                    help="only time a plain device-to-device copy of GIB GiB (the reference "
+                         "for measured HBM bandwidth and for the PMC byte-counter scale)")
+    ap.add_argument("--only", choices=("f64", "f32"), default=None,
+                    help="time one precision only (profiling runs)")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the volume term has no cross-GPU exchange, "
@@ -118,6 +123,16 @@ def main(argv=None):
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
 
+    if a.copy_probe > 0:
+        n = int(a.copy_probe * (1 << 30)) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        ms, _ = time_launches(lambda: dst.copy_(src), a.steps, a.warmup, stream)
+        moved = 2 * n * 8
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                          "ms_per_copy": ms, "copy_GBs": moved / (ms * 1e-3) / 1e9}), flush=True)
+        return 0
+
     t0 = time.perf_counter()
     w = I.warped_workload()                      # N=7, 32768 elements, seed k=2
     Ne, Nq = w.Ne, w.Nq
@@ -129,6 +144,8 @@ def main(argv=None):
     results = {}
     ref64 = oracle.volume_rhs(w.D, w.geo, w.q, w.rho_ref, w.theta_ref, phys)
     for tag, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        if a.only and tag != a.only:
+            continue
         src = w if dt == torch.float64 else I.to_fp32(w)
         q, geo, D = dev(src.q), dev(src.geo), dev(src.D)
         rr, tr = dev(src.rho_ref), dev(src.theta_ref)
@@ -151,6 +168,11 @@ def main(argv=None):
         del q, geo, D, rr, tr, out
         torch.cuda.empty_cache()
 
+    if a.only:
+        r = results[a.only]
+        print(json.dumps({"only": a.only, "ms_per_step": r["ms"], "GBs": r["gbs"],
+                          "err": r["err"]}), flush=True)
+        return 0
     r64, r32 = results["f64"], results["f32"]
     traffic = measured_traffic("volume_f64_n7")
     line = {
