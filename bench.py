@@ -9,6 +9,10 @@ term (one kernel launch over all elements) with inputs resident in HBM.
 ``value`` is the FP64 rate; the FP32 form of the same workload is reported
 beside it, with its error against the FP64 oracle and the FP32/FP64 speedup.
 
+Beside it the line carries the mixed-order persistent batch (N = 3, 5, 7, 9,
+5000 elements each; autotuned), one SSP-RK3 step replayed from a HIP graph,
+and the adjoint (N=7, 8192 elements), each in FP64 and FP32.
+
 Prints one JSON line.  ``roofline`` prices the FP64 volume kernel against
 the 8 TB/s HBM peak using the algorithmic bytes per node (176 B in FP64,
 92 B in FP32); its duration is measured with HIP events on the launch
@@ -78,6 +82,67 @@ def time_launches(fn, steps: int, warmup: int, stream):
     return start.elapsed_time(end) / steps, wall
 
 
+def bench_batch_and_rk3(sv, I, steps: int, warmup: int, stream):
+    """Mixed-order batch (N = 3, 5, 7, 9; 5000 warped elements each) as one
+    persistent launch, autotuned, and one SSP-RK3 step (dt = 1e-3) replayed
+    from a HIP graph; FP64 and FP32.  Returns timings and algorithmic rates."""
+    import torch
+    ws = I.mixed_order_workloads()
+    nodes = sum(w.Ne * w.Nq ** 3 for w in ws)
+    out = {"workload": "N=3,5,7,9 x 5000 warped elements (8.96 M nodes)", "nodes": nodes}
+    for tag, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        cast = (lambda a: a) if dt == torch.float64 else (lambda a: np.asarray(a, np.float32))
+        sizes = [w.q.size for w in ws]
+        n = sum(sizes)
+        q_n = torch.from_numpy(np.concatenate([cast(w.q).ravel() for w in ws])).cuda()
+        q_1, q_2, L = (torch.empty_like(q_n) for _ in range(3))
+        blocks, off = [], 0
+        for w, sz in zip(ws, sizes):
+            blocks.append(dict(q=q_n[off:off + sz].view(w.q.shape),
+                               geo=torch.from_numpy(cast(w.geo)).cuda(),
+                               D=torch.from_numpy(cast(w.D)).cuda(),
+                               rho_ref=torch.from_numpy(cast(w.rho_ref)).cuda(),
+                               theta_ref=torch.from_numpy(w.theta_ref).cuda(),
+                               rhs=L[off:off + sz].view(w.q.shape)))
+            off += sz
+        plan = sv.BatchPlan(blocks, ws[0].phys.as_tuple(), autotune=True)
+        ms_rhs, _ = time_launches(plan.execute, steps, warmup, stream)
+        g = sv.RK3Graph(blocks, q_n, q_1, q_2, L, 1e-3, ws[0].phys.as_tuple())
+        ms_rk, _ = time_launches(g.step, steps, warmup, stream)
+        bpn = BYTES_PER_NODE[tag]
+        esz = 8 if tag == "f64" else 4
+        # RK step: 3 x (RHS + axpby); axpby reads 3 (2 in stage 1) and writes 1 value per dof
+        rk_bytes = 3 * bpn * nodes + (4 + 4 + 3) * esz * n
+        out[tag] = {"rhs_ms": ms_rhs, "rhs_el_s": sum(w.Ne for w in ws) / (ms_rhs * 1e-3),
+                    "rhs_GBs": bpn * nodes / (ms_rhs * 1e-3) / 1e9,
+                    "rk3_step_ms": ms_rk, "rk3_GBs": rk_bytes / (ms_rk * 1e-3) / 1e9,
+                    "plan": plan.describe()}
+        g.close()
+        plan.close()
+        del q_n, q_1, q_2, L, blocks
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_adjoint(sv, I, steps: int, warmup: int, stream):
+    """Vector-Jacobian product at N=7 on the first 8192 warped elements."""
+    import torch
+    w = I.adjoint_workload()
+    nodes = w.Ne * w.Nq ** 3
+    out = {"workload": "adjoint, N=7, 8192 warped elements", "nodes": nodes}
+    for tag, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        src = w if dt == torch.float64 else I.to_fp32(w)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        q, geo, D, lam = t(src.q), t(src.geo), t(src.D), t(src.lam)
+        mu = torch.empty_like(q)
+        ms, _ = time_launches(lambda: sv.volume_rhs_adjoint(q, geo, D, lam, w.phys.as_tuple(), out=mu),
+                              steps, warmup, stream)
+        esz = 8 if tag == "f64" else 4
+        out[tag] = {"ms": ms, "el_s": w.Ne / (ms * 1e-3),
+                    "GBs": 25 * esz * nodes / (ms * 1e-3) / 1e9}
+    return out
+
+
 def cpu_baseline(w, budget_s: float):
     import oracle
     phys = w.phys.as_tuple()
@@ -103,6 +168,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the mixed-order batch / RK3 graph and adjoint measurements")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only time a plain device-to-device copy of GIB GiB (the reference "
                          "for measured HBM bandwidth and for the PMC byte-counter scale)")
@@ -202,6 +269,9 @@ def main(argv=None):
         "roofline": {"bound": "hbm", "achieved": r64["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r64["gbs"] / HBM_PEAK_GBS, "traffic": traffic},
     }
+    if not a.no_extra:
+        line["batch_mixed_order"] = bench_batch_and_rk3(sv, I, a.steps, a.warmup, stream)
+        line["adjoint"] = bench_adjoint(sv, I, a.steps, a.warmup, stream)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(line), flush=True)
