@@ -81,11 +81,17 @@ typedef struct sem_phys {
     double grav;
 } sem_phys;
 
-/* Tile shape of the single-order kernels: elements per workgroup.
- * 0 selects the built-in default for (dtype, Nq). */
+/* Tile shape of the single-order kernels: elements per workgroup and LDS
+ * layout.  SEM_LAYOUT_FULL stages the contravariant fluxes of all three
+ * reference directions in LDS (one barrier); SEM_LAYOUT_ALIAS stages one
+ * direction at a time (a third of the LDS, three barriers).  Zeros select the
+ * built-in default for (dtype, Nq). */
+#define SEM_LAYOUT_DEFAULT 0
+#define SEM_LAYOUT_FULL 1
+#define SEM_LAYOUT_ALIAS 2
 typedef struct sem_tile {
     int32_t elems_per_block;
-    int32_t reserved;
+    int32_t layout;
 } sem_tile;
 
 /* Thread-local text describing the last non-OK status of this thread. */
@@ -113,18 +119,19 @@ sem_status sem_volume_rhs(int32_t Ne, int32_t Nq, sem_dtype dtype,
                           const sem_phys* phys, void* rhs, int32_t accumulate,
                           void* stream);
 
-/* As sem_volume_rhs, with an explicit tile shape (NULL = default).  An
- * elems_per_block value that is not compiled for (dtype, Nq) returns
- * SEM_ERR_UNSUPPORTED. */
+/* As sem_volume_rhs, with an explicit tile shape (NULL = default).  A shape
+ * that is not compiled for (dtype, Nq) returns SEM_ERR_UNSUPPORTED, an
+ * unknown layout code SEM_ERR_INVALID_ARG.  Every shape computes the same
+ * values (up to the order of floating-point additions). */
 sem_status sem_volume_rhs_tiled(int32_t Ne, int32_t Nq, sem_dtype dtype,
                                 const void* D, const void* geo, const void* q,
                                 const void* rho_ref, const double* theta_ref,
                                 const sem_phys* phys, void* rhs, int32_t accumulate,
                                 const sem_tile* tile, void* stream);
 
-/* Writes up to `cap` supported elems_per_block values for (dtype, Nq) into
- * `out` and returns how many exist (0 for an unsupported Nq). */
-int32_t sem_tile_options(sem_dtype dtype, int32_t Nq, int32_t* out, int32_t cap);
+/* Writes up to `cap` compiled tile shapes for (dtype, Nq) into `out` and
+ * returns how many exist (0 for an unsupported Nq or dtype). */
+int32_t sem_tile_options(sem_dtype dtype, int32_t Nq, sem_tile* out, int32_t cap);
 
 /*
  * Vector-Jacobian product of the volume term with respect to the state
@@ -163,12 +170,16 @@ typedef struct sem_block {
 
 typedef struct sem_plan_s* sem_plan;
 
-#define SEM_PLAN_AUTOTUNE 1u   /* time candidate tile shapes on the device (synchronises) */
+#define SEM_PLAN_AUTOTUNE 1u   /* time candidate tile shapes on the device (synchronises;
+                                  the timing launches write the blocks' rhs arrays) */
 #define SEM_PLAN_USE_CACHE 2u  /* read/write tuned shapes in the JSON file named by the
                                   SEM_PLAN_CACHE environment variable (ignored if unset) */
 
 /* Builds a plan: picks a tile shape per order (autotuned or default), orders
  * the tiles longest-first and uploads a device tile table owned by the plan.
+ * One launch has one workgroup size and one LDS size (its largest shape's);
+ * the autotuner times every order's candidate shapes at each possible LDS
+ * size and keeps the combination with the smallest total time.
  * The block pointers are baked in: the caller keeps those buffers alive and
  * unchanged in address for the plan's lifetime.  Errors: nblocks < 1, any
  * invalid block (as sem_volume_rhs), SEM_ERR_NO_MEMORY, SEM_ERR_HIP. */
@@ -188,15 +199,24 @@ sem_status sem_plan_describe(sem_plan plan, char* buf, int32_t len);
 sem_status sem_plan_destroy(sem_plan plan);
 
 /* ---------------------------------------------------------------------------
- * One SSP-RK3 (Shu-Osher) step of dq/dt = v(q), captured once in a HIP graph:
+ * One SSP-RK3 (Shu-Osher) step of dq/dt = v(q) (explicit time integration of
+ * the method-of-lines rate, Sec. 2), captured once in a HIP graph:
  *   q1 = q + dt v(q);  q2 = 3/4 q + 1/4 (q1 + dt v(q1));
  *   q  = 1/3 q + 2/3 (q2 + dt v(q2))          (q updated in place)
- * Each stage is one persistent batch launch plus one sem_axpby.
+ * By default each stage is ONE persistent batch launch whose epilogue writes
+ * the stage update directly (the rate is never stored).  With
+ * SEM_RK3_SEPARATE_STAGES each stage is a batch launch writing v into L plus
+ * one sem_axpby.
  * q_n, q_1, q_2, L are flat buffers of n values of dtype; every block's q
  * must lie inside q_n and its rhs inside L at the same offset (the stage
- * plans read q_1 and q_2 at that offset).  L receives the last stage's rate.
+ * plans read q_1 and q_2 at that offset).  L is written only with
+ * SEM_RK3_SEPARATE_STAGES (then it holds the last stage's rate).
+ * flags: SEM_PLAN_AUTOTUNE / SEM_PLAN_USE_CACHE (tile shapes, chosen once and
+ * shared by the three stages) and SEM_RK3_SEPARATE_STAGES.
  * ------------------------------------------------------------------------- */
 typedef struct sem_rk3_s* sem_rk3;
+
+#define SEM_RK3_SEPARATE_STAGES 4u
 
 sem_status sem_rk3_graph_create(const sem_block* blocks, int32_t nblocks, sem_dtype dtype,
                                 const sem_phys* phys, uint32_t flags, void* q_n, void* q_1,
@@ -205,6 +225,9 @@ sem_status sem_rk3_graph_create(const sem_block* blocks, int32_t nblocks, sem_dt
 
 /* Launches the captured step on `stream`.  Allocates nothing. */
 sem_status sem_rk3_graph_launch(sem_rk3 step, void* stream);
+
+/* Writes a JSON description (stage mode and the shared stage plan). */
+sem_status sem_rk3_graph_describe(sem_rk3 step, char* buf, int32_t len);
 
 /* Frees the graph and its three stage plans. */
 sem_status sem_rk3_graph_destroy(sem_rk3 step);

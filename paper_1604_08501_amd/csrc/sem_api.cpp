@@ -61,7 +61,7 @@ semk::Phys to_phys(const sem_phys* p)
 constexpr int kMinNq = 2, kMaxNq = 10;
 
 // Built-in tile shapes for the single-order kernels: about 256 threads for
-// small orders, one element per workgroup from Nq = 6 on.
+// small orders, one element per workgroup from Nq = 6 on, all fluxes in LDS.
 int default_epb(int nq)
 {
     switch (nq) {
@@ -72,6 +72,19 @@ int default_epb(int nq)
     default: return 1;
     }
 }
+
+// public layout code (sem_tile.layout) -> internal layout, -1 if unknown
+int internal_layout(int32_t code)
+{
+    switch (code) {
+    case SEM_LAYOUT_DEFAULT:
+    case SEM_LAYOUT_FULL: return semk::FULL;
+    case SEM_LAYOUT_ALIAS: return semk::ALIAS;
+    default: return -1;
+    }
+}
+
+int32_t public_layout(int lay) { return lay == semk::ALIAS ? SEM_LAYOUT_ALIAS : SEM_LAYOUT_FULL; }
 
 sem_status check_dtype(sem_dtype dt)
 {
@@ -135,17 +148,16 @@ semk::BlockPtrs<T> block_ptrs(int64_t Ne, const void* D, const void* geo, const 
     return semk::BlockPtrs<T>{static_cast<const T*>(D),   static_cast<const T*>(geo),
                               static_cast<const T*>(q),   static_cast<const T*>(rho_ref),
                               theta_ref,                  static_cast<T*>(rhs),
-                              Ne};
+                              Ne,                         nullptr};
 }
 
-int tile_options(sem_dtype dt, int nq, int* out, int cap)
+int tile_options(int nq, sem_tile* out, int cap)
 {
-    (void)dt;   // every compiled shape exists for both dtypes
     int n = 0;
     for (int i = 0; i < semh::kNumVariants; ++i)
         if (semh::kVariants[i].nq == nq) {
             if (n < cap && out)
-                out[n] = semh::kVariants[i].epb;
+                out[n] = sem_tile{semh::kVariants[i].epb, public_layout(semh::kVariants[i].lay)};
             ++n;
         }
     return n;
@@ -160,11 +172,11 @@ extern "C" const char* sem_last_error(void) { return g_last_error.c_str(); }
 
 extern "C" const char* sem_version(void) { return "semvol 0.1.0 (gfx950)"; }
 
-extern "C" int32_t sem_tile_options(sem_dtype dtype, int32_t Nq, int32_t* out, int32_t cap)
+extern "C" int32_t sem_tile_options(sem_dtype dtype, int32_t Nq, sem_tile* out, int32_t cap)
 {
     if (dtype != SEM_F64 && dtype != SEM_F32)
-        return 0;
-    return tile_options(dtype, Nq, out, cap);
+        return 0;   // every compiled shape exists for both dtypes
+    return tile_options(Nq, out, cap);
 }
 
 extern "C" sem_status sem_volume_rhs_tiled(int32_t Ne, int32_t Nq, sem_dtype dtype, const void* D,
@@ -173,18 +185,25 @@ extern "C" sem_status sem_volume_rhs_tiled(int32_t Ne, int32_t Nq, sem_dtype dty
                                            int32_t accumulate, const sem_tile* tile, void* stream)
 {
     SEM_TRY(check_volume_args(Ne, Nq, dtype, D, geo, q, rho_ref, theta_ref, phys, rhs));
-    int epb = tile && tile->elems_per_block > 0 ? tile->elems_per_block : default_epb(Nq);
-    if (semh::variant_index(Nq, epb) < 0)
-        return fail(SEM_ERR_UNSUPPORTED, "elems_per_block = %d is not compiled for Nq = %d", epb, Nq);
+    const int epb = tile && tile->elems_per_block > 0 ? tile->elems_per_block : default_epb(Nq);
+    const int lay = internal_layout(tile ? tile->layout : SEM_LAYOUT_DEFAULT);
+    if (lay < 0)
+        return fail(SEM_ERR_INVALID_ARG, "unknown tile layout %d", tile->layout);
+    if (semh::variant_index(Nq, epb, lay) < 0)
+        return fail(SEM_ERR_UNSUPPORTED,
+                    "tile (elems_per_block = %d, layout = %d) is not compiled for Nq = %d", epb,
+                    (int)public_layout(lay), Nq);
     const semk::Phys ph = to_phys(phys);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t err;
     if (dtype == SEM_F64)
         err = semh::launch_volume<double>(
-            Nq, epb, block_ptrs<double>(Ne, D, geo, q, rho_ref, theta_ref, rhs), ph, accumulate, s);
+            Nq, epb, lay, block_ptrs<double>(Ne, D, geo, q, rho_ref, theta_ref, rhs), ph, accumulate,
+            s);
     else
         err = semh::launch_volume<float>(
-            Nq, epb, block_ptrs<float>(Ne, D, geo, q, rho_ref, theta_ref, rhs), ph, accumulate, s);
+            Nq, epb, lay, block_ptrs<float>(Ne, D, geo, q, rho_ref, theta_ref, rhs), ph, accumulate,
+            s);
     if (err != hipSuccess)
         return hip_fail(err, "volume kernel launch");
     return SEM_OK;
@@ -273,6 +292,7 @@ namespace {
 struct OrderChoice {
     int nq = 0;
     int epb = 0;
+    int lay = semk::FULL;
     double us = -1.0;        // measured time of this order alone (autotuned), else -1
     int64_t elements = 0;
 };
@@ -285,8 +305,11 @@ struct PlanCore {
     int lds_bytes = 0;
     int ntiles = 0;
     int device = 0;
+    bool rk = false;                    // fused Runge-Kutta stage epilogue
+    semk::RkStage rk_stage{0.0, 0.0, 0.0};
     std::vector<sem_block> blocks;
-    std::vector<OrderChoice> orders;   // one per distinct Nq
+    std::vector<const void*> rk_x;      // per block, fused stage only
+    std::vector<OrderChoice> orders;    // one per distinct Nq
     semh::Tile* d_tiles = nullptr;
     void* d_blocks = nullptr;
     bool autotuned = false;
@@ -317,13 +340,26 @@ sem_status check_block(const sem_block& b, int idx, sem_dtype dt, const sem_phys
 }
 
 template <typename T>
-std::vector<semk::BlockPtrs<T>> host_block_table(const std::vector<sem_block>& blocks)
+std::vector<semk::BlockPtrs<T>> host_block_table(const PlanCore& p)
 {
     std::vector<semk::BlockPtrs<T>> v;
-    v.reserve(blocks.size());
-    for (const sem_block& b : blocks)
-        v.push_back(block_ptrs<T>(b.Ne, b.D, b.geo, b.q, b.rho_ref, b.theta_ref, b.rhs));
+    v.reserve(p.blocks.size());
+    for (size_t i = 0; i < p.blocks.size(); ++i) {
+        const sem_block& b = p.blocks[i];
+        semk::BlockPtrs<T> bp = block_ptrs<T>(b.Ne, b.D, b.geo, b.q, b.rho_ref, b.theta_ref, b.rhs);
+        if (p.rk)
+            bp.rk_x = static_cast<const T*>(p.rk_x[i]);
+        v.push_back(bp);
+    }
     return v;
+}
+
+const OrderChoice& choice_for(const std::vector<OrderChoice>& orders, int nq)
+{
+    for (const OrderChoice& o : orders)
+        if (o.nq == nq)
+            return o;
+    return orders.front();   // unreachable: every block's order has a choice
 }
 
 // Tiles of every block whose order is in `only_nq` (all if 0), sorted by
@@ -340,18 +376,14 @@ std::vector<semh::Tile> make_tiles(const std::vector<sem_block>& blocks,
         const sem_block& b = blocks[bi];
         if (only_nq && b.Nq != only_nq)
             continue;
-        const OrderChoice* oc = nullptr;
-        for (const OrderChoice& o : orders)
-            if (o.nq == b.Nq)
-                oc = &o;
-        const int epb = oc->epb;
-        const int vid = semh::variant_index(b.Nq, epb);
+        const OrderChoice& oc = choice_for(orders, b.Nq);
+        const int vid = semh::variant_index(b.Nq, oc.epb, oc.lay);
         const double nodes = (double)b.Nq * b.Nq * b.Nq;
         // measured per-element time when autotuned, else a node count
-        const double per_elem = (oc->us > 0 && oc->elements > 0) ? oc->us / oc->elements : nodes;
-        for (int64_t e0 = 0; e0 < b.Ne; e0 += epb) {
-            const int ne = (int)std::min<int64_t>(epb, b.Ne - e0);
-            items.push_back({semh::Tile{(int32_t)bi, vid, ne, 0, e0}, per_elem * epb});
+        const double per_elem = (oc.us > 0 && oc.elements > 0) ? oc.us / oc.elements : nodes;
+        for (int64_t e0 = 0; e0 < b.Ne; e0 += oc.epb) {
+            const int ne = (int)std::min<int64_t>(oc.epb, b.Ne - e0);
+            items.push_back({semh::Tile{(int32_t)bi, vid, ne, 0, e0}, per_elem * oc.epb});
         }
     }
     std::stable_sort(items.begin(), items.end(),
@@ -363,51 +395,65 @@ std::vector<semh::Tile> make_tiles(const std::vector<sem_block>& blocks,
     return out;
 }
 
-int lds_for(sem_dtype dt, int nt, const std::vector<OrderChoice>& orders, int only_nq)
+int shape_lds(sem_dtype dt, int nt, int nq, int epb, int lay)
+{
+    return dt == SEM_F64 ? semh::batch_lds_bytes<double>(nt, nq, epb, lay)
+                         : semh::batch_lds_bytes<float>(nt, nq, epb, lay);
+}
+
+int lds_for(sem_dtype dt, int nt, const std::vector<OrderChoice>& orders)
 {
     int lds = 0;
-    for (const OrderChoice& o : orders) {
-        if (only_nq && o.nq != only_nq)
-            continue;
-        const int b = dt == SEM_F64 ? semh::batch_lds_bytes<double>(nt, o.nq, o.epb)
-                                    : semh::batch_lds_bytes<float>(nt, o.nq, o.epb);
-        lds = std::max(lds, b);
-    }
+    for (const OrderChoice& o : orders)
+        lds = std::max(lds, shape_lds(dt, nt, o.nq, o.epb, o.lay));
     return lds;
 }
 
-bool variant_ok(sem_dtype dt, int nt, int nq, int epb)
+bool variant_ok(sem_dtype dt, int nt, int nq, int epb, int lay, bool rk)
 {
-    return dt == SEM_F64 ? semh::batch_variant_ok<double>(nt, nq, epb)
-                         : semh::batch_variant_ok<float>(nt, nq, epb);
+    return dt == SEM_F64 ? semh::batch_variant_ok<double>(nt, nq, epb, lay, rk)
+                         : semh::batch_variant_ok<float>(nt, nq, epb, lay, rk);
 }
 
-hipError_t occupancy(sem_dtype dt, int nt, int lds, int* bpc)
+hipError_t occupancy(sem_dtype dt, int nt, int lds, bool rk, int* bpc)
 {
-    return dt == SEM_F64 ? semh::batch_blocks_per_cu<double>(nt, lds, bpc)
-                         : semh::batch_blocks_per_cu<float>(nt, lds, bpc);
+    return dt == SEM_F64 ? semh::batch_blocks_per_cu<double>(nt, lds, rk, bpc)
+                         : semh::batch_blocks_per_cu<float>(nt, lds, rk, bpc);
 }
 
 hipError_t launch(const PlanCore& p, const semh::Tile* d_tiles, int ntiles, int grid, int lds,
                   hipStream_t s)
 {
+    const semk::RkStage* rk = p.rk ? &p.rk_stage : nullptr;
     if (p.dtype == SEM_F64)
         return semh::launch_batch<double>(p.nt, d_tiles, ntiles,
                                           static_cast<const semk::BlockPtrs<double>*>(p.d_blocks),
-                                          p.phys, grid, lds, s);
+                                          p.phys, rk, grid, lds, s);
     return semh::launch_batch<float>(p.nt, d_tiles, ntiles,
                                      static_cast<const semk::BlockPtrs<float>*>(p.d_blocks), p.phys,
-                                     grid, lds, s);
+                                     rk, grid, lds, s);
 }
 
-// Upload the block table and the tile table for the current choices; fix
-// the grid from the occupancy of the chosen workgroup size and LDS.
-sem_status finalize(PlanCore& p, hipStream_t s)
+sem_status resident_grid(const PlanCore& p, int ntiles, int lds, int* grid)
 {
-    free_core(&p);
-    std::vector<semh::Tile> tiles = make_tiles(p.blocks, p.orders, 0);
-    p.ntiles = (int)tiles.size();
-    p.lds_bytes = lds_for(p.dtype, p.nt, p.orders, 0);
+    int bpc = 0, ncu = 0;
+    hipError_t err = occupancy(p.dtype, p.nt, lds, p.rk, &bpc);
+    if (err != hipSuccess)
+        return hip_fail(err, "occupancy query");
+    err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p.device);
+    if (err != hipSuccess)
+        return hip_fail(err, "CU count query");
+    if (bpc < 1)
+        return fail(SEM_ERR_UNSUPPORTED, "batch kernel cannot be resident with %d B of LDS", lds);
+    *grid = std::max(1, std::min(ntiles, bpc * ncu));
+    return SEM_OK;
+}
+
+sem_status upload_blocks(PlanCore& p, hipStream_t s)
+{
+    if (p.d_blocks)
+        (void)hipFree(p.d_blocks);
+    p.d_blocks = nullptr;
     const size_t bt_bytes = p.blocks.size() *
                             (p.dtype == SEM_F64 ? sizeof(semk::BlockPtrs<double>)
                                                 : sizeof(semk::BlockPtrs<float>));
@@ -415,48 +461,57 @@ sem_status finalize(PlanCore& p, hipStream_t s)
     if (err != hipSuccess)
         return fail(SEM_ERR_NO_MEMORY, "plan block table (%zu B): %s", bt_bytes,
                     hipGetErrorString(err));
-    err = hipMalloc((void**)&p.d_tiles, tiles.size() * sizeof(semh::Tile));
-    if (err != hipSuccess)
-        return fail(SEM_ERR_NO_MEMORY, "plan tile table: %s", hipGetErrorString(err));
     if (p.dtype == SEM_F64) {
-        auto hb = host_block_table<double>(p.blocks);
+        auto hb = host_block_table<double>(p);
         err = hipMemcpyAsync(p.d_blocks, hb.data(), bt_bytes, hipMemcpyHostToDevice, s);
         if (err == hipSuccess)
             err = hipStreamSynchronize(s);
     } else {
-        auto hb = host_block_table<float>(p.blocks);
+        auto hb = host_block_table<float>(p);
         err = hipMemcpyAsync(p.d_blocks, hb.data(), bt_bytes, hipMemcpyHostToDevice, s);
         if (err == hipSuccess)
             err = hipStreamSynchronize(s);
     }
     if (err != hipSuccess)
         return hip_fail(err, "upload block table");
+    return SEM_OK;
+}
+
+// Upload the tile table for the current choices and fix the grid from the
+// occupancy of the chosen workgroup size and LDS.
+sem_status finalize(PlanCore& p, hipStream_t s)
+{
+    SEM_TRY(upload_blocks(p, s));
+    if (p.d_tiles)
+        (void)hipFree(p.d_tiles);
+    p.d_tiles = nullptr;
+    std::vector<semh::Tile> tiles = make_tiles(p.blocks, p.orders, 0);
+    p.ntiles = (int)tiles.size();
+    p.lds_bytes = lds_for(p.dtype, p.nt, p.orders);
+    hipError_t err = hipMalloc((void**)&p.d_tiles, tiles.size() * sizeof(semh::Tile));
+    if (err != hipSuccess)
+        return fail(SEM_ERR_NO_MEMORY, "plan tile table: %s", hipGetErrorString(err));
     err = hipMemcpyAsync(p.d_tiles, tiles.data(), tiles.size() * sizeof(semh::Tile),
                          hipMemcpyHostToDevice, s);
     if (err == hipSuccess)
         err = hipStreamSynchronize(s);
     if (err != hipSuccess)
         return hip_fail(err, "upload tile table");
-    int bpc = 0, ncu = 0;
-    err = occupancy(p.dtype, p.nt, p.lds_bytes, &bpc);
-    if (err != hipSuccess)
-        return hip_fail(err, "occupancy query");
-    err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p.device);
-    if (err != hipSuccess)
-        return hip_fail(err, "CU count query");
-    if (bpc < 1)
-        return fail(SEM_ERR_UNSUPPORTED, "batch kernel cannot be resident with %d B of LDS",
-                    p.lds_bytes);
-    p.grid = std::max(1, std::min(p.ntiles, bpc * ncu));
-    return SEM_OK;
+    return resident_grid(p, p.ntiles, p.lds_bytes, &p.grid);
 }
 
 // ---------------------------------------------------------------------------
-// Plan cache: a flat JSON object {"key": {"epb": E, "us": T}, ...} in the
-// file named by SEM_PLAN_CACHE, keyed by device arch, dtype, workgroup size,
-// Nq and a power-of-two element-count bucket.
+// Plan cache: a flat JSON object {"key": {"epb": E, "layout": L, "us": T}} in
+// the file named by SEM_PLAN_CACHE, keyed by device arch, dtype, workgroup
+// size, the LDS cap of the launch, Nq and a power-of-two element bucket.
 // ---------------------------------------------------------------------------
 std::mutex g_cache_mu;
+
+struct CacheEntry {
+    int epb = 0;
+    int lay = 0;
+    double us = -1.0;
+};
 
 std::string cache_path()
 {
@@ -474,20 +529,33 @@ std::string arch_name(int device)
     return c == std::string::npos ? a : a.substr(0, c);
 }
 
-std::string cache_key(const std::string& arch, sem_dtype dt, int nt, int nq, int64_t ne)
+std::string cache_key(const std::string& arch, sem_dtype dt, bool rk, int nt, int cap, int nq,
+                      int64_t ne)
 {
     int64_t bucket = 1;
     while (bucket < ne)
         bucket <<= 1;
-    char buf[128];
-    snprintf(buf, sizeof buf, "%s/%s/nt%d/nq%d/ne%lld", arch.c_str(), dt == SEM_F64 ? "f64" : "f32",
-             nt, nq, (long long)bucket);
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s/%s%s/nt%d/lds%d/nq%d/ne%lld", arch.c_str(),
+             dt == SEM_F64 ? "f64" : "f32", rk ? "-rk" : "", nt, cap, nq, (long long)bucket);
     return buf;
 }
 
-std::map<std::string, std::pair<int, double>> cache_read(const std::string& path)
+double json_number(const std::string& body, const char* name, double dflt)
 {
-    std::map<std::string, std::pair<int, double>> m;
+    const std::string key = std::string("\"") + name + "\"";
+    size_t k = body.find(key);
+    if (k == std::string::npos)
+        return dflt;
+    size_t c = body.find(':', k);
+    if (c == std::string::npos)
+        return dflt;
+    return atof(body.c_str() + c + 1);
+}
+
+std::map<std::string, CacheEntry> cache_read(const std::string& path)
+{
+    std::map<std::string, CacheEntry> m;
     FILE* f = fopen(path.c_str(), "rb");
     if (!f)
         return m;
@@ -511,22 +579,18 @@ std::map<std::string, std::pair<int, double>> cache_read(const std::string& path
         if (ob == std::string::npos || cb == std::string::npos || cb < ob)
             break;
         std::string body = s.substr(ob, cb - ob);
-        int epb = 0;
-        double us = -1.0;
-        size_t e = body.find("\"epb\"");
-        size_t u = body.find("\"us\"");
-        if (e != std::string::npos)
-            epb = atoi(body.c_str() + body.find(':', e) + 1);
-        if (u != std::string::npos)
-            us = atof(body.c_str() + body.find(':', u) + 1);
-        if (epb > 0)
-            m[key] = {epb, us};
+        CacheEntry e;
+        e.epb = (int)json_number(body, "epb", 0);
+        e.lay = (int)json_number(body, "layout", 0);
+        e.us = json_number(body, "us", -1.0);
+        if (e.epb > 0)
+            m[key] = e;
         pos = cb + 1;
     }
     return m;
 }
 
-void cache_write(const std::string& path, const std::map<std::string, std::pair<int, double>>& m)
+void cache_write(const std::string& path, const std::map<std::string, CacheEntry>& m)
 {
     std::string tmp = path + ".tmp";
     FILE* f = fopen(tmp.c_str(), "wb");
@@ -534,57 +598,49 @@ void cache_write(const std::string& path, const std::map<std::string, std::pair<
         return;
     fprintf(f, "{\n");
     size_t i = 0;
-    for (const auto& kv : m) {
-        fprintf(f, "  \"%s\": {\"epb\": %d, \"us\": %.3f}%s\n", kv.first.c_str(), kv.second.first,
-                kv.second.second, ++i < m.size() ? "," : "");
-    }
+    for (const auto& kv : m)
+        fprintf(f, "  \"%s\": {\"epb\": %d, \"layout\": %d, \"us\": %.3f}%s\n", kv.first.c_str(),
+                kv.second.epb, kv.second.lay, kv.second.us, ++i < m.size() ? "," : "");
     fprintf(f, "}\n");
     fclose(f);
     rename(tmp.c_str(), path.c_str());
 }
 
-// Time one order's blocks alone with a candidate shape: median of 5 launches
-// after 2 warm-ups, with HIP events on the plan stream.
-sem_status time_candidate(PlanCore& p, int nq, hipStream_t s, double* us_out)
+// Time one order's blocks alone with the shape currently in p.orders, under
+// the dynamic LDS `cap` that the combined launch will use (it sets the
+// occupancy): median of 5 launches after 2 warm-ups, HIP events.
+sem_status time_candidate(PlanCore& p, int nq, int cap, hipStream_t s, double* us_out)
 {
     std::vector<semh::Tile> tiles = make_tiles(p.blocks, p.orders, nq);
-    const int lds = lds_for(p.dtype, p.nt, p.orders, nq);
+    int grid = 0;
+    SEM_TRY(resident_grid(p, (int)tiles.size(), cap, &grid));
     semh::Tile* d_t = nullptr;
     hipError_t err = hipMalloc((void**)&d_t, tiles.size() * sizeof(semh::Tile));
     if (err != hipSuccess)
         return fail(SEM_ERR_NO_MEMORY, "autotune tile table: %s", hipGetErrorString(err));
     err = hipMemcpy(d_t, tiles.data(), tiles.size() * sizeof(semh::Tile), hipMemcpyHostToDevice);
-    int bpc = 0, ncu = 0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     if (err == hipSuccess)
-        err = occupancy(p.dtype, p.nt, lds, &bpc);
+        err = hipEventCreate(&e0);
     if (err == hipSuccess)
-        err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p.device);
-    if (err != hipSuccess) {
-        (void)hipFree(d_t);
-        return hip_fail(err, "autotune setup");
-    }
-    if (bpc < 1) {
-        (void)hipFree(d_t);
-        *us_out = 1e30;
-        return SEM_OK;
-    }
-    const int grid = std::max(1, std::min((int)tiles.size(), bpc * ncu));
-    hipEvent_t e0, e1;
-    (void)hipEventCreate(&e0);
-    (void)hipEventCreate(&e1);
+        err = hipEventCreate(&e1);
     std::vector<float> ms;
     for (int r = 0; r < 7 && err == hipSuccess; ++r) {
-        (void)hipEventRecord(e0, s);
-        err = launch(p, d_t, (int)tiles.size(), grid, lds, s);
-        (void)hipEventRecord(e1, s);
+        err = hipEventRecord(e0, s);
+        if (err == hipSuccess)
+            err = launch(p, d_t, (int)tiles.size(), grid, cap, s);
+        if (err == hipSuccess)
+            err = hipEventRecord(e1, s);
         if (err == hipSuccess)
             err = hipEventSynchronize(e1);
         float t = 0.f;
         if (err == hipSuccess && r >= 2 && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
             ms.push_back(t);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
     (void)hipFree(d_t);
     if (err != hipSuccess)
         return hip_fail(err, "autotune launch");
@@ -593,78 +649,98 @@ sem_status time_candidate(PlanCore& p, int nq, hipStream_t s, double* us_out)
     return SEM_OK;
 }
 
+// For every workgroup size and every LDS cap (the LDS of a compiled shape),
+// pick per order the fastest shape that fits under the cap, timed at that
+// cap; keep the (size, cap) whose per-order times sum lowest.  The launch's
+// occupancy is set by its largest shape, so timing each order at the cap it
+// will share is what makes the per-order choices add up.
 sem_status autotune(PlanCore& p, bool use_cache, hipStream_t s)
 {
     const std::string arch = arch_name(p.device);
     const std::string path = use_cache ? cache_path() : std::string();
-    std::map<std::string, std::pair<int, double>> cache;
+    std::map<std::string, CacheEntry> cache;
     if (!path.empty()) {
         std::lock_guard<std::mutex> lk(g_cache_mu);
         cache = cache_read(path);
     }
+    SEM_TRY(upload_blocks(p, s));
     bool all_cached = true;
     double best_total = 1e300;
-    int best_nt = 256;
+    int best_nt = 0, best_cap = 0;
     std::vector<OrderChoice> best_orders;
-    // upload a block table for the timing launches
-    p.nt = 256;
-    {
-        std::vector<OrderChoice> saved = p.orders;
-        for (OrderChoice& o : p.orders)
-            o.epb = default_epb(o.nq);
-        sem_status st = finalize(p, s);
-        if (st != SEM_OK)
-            return st;
-        p.orders = saved;
-    }
     for (int nt : semh::kBatchThreads) {
         p.nt = nt;
-        double total = 0.0;
-        std::vector<OrderChoice> chosen = p.orders;
-        for (OrderChoice& oc : chosen) {
-            const std::string key = cache_key(arch, p.dtype, nt, oc.nq, oc.elements);
-            auto it = cache.find(key);
-            if (it != cache.end() && variant_ok(p.dtype, nt, oc.nq, it->second.first)) {
-                oc.epb = it->second.first;
-                oc.us = it->second.second;
-                total += oc.us;
-                continue;
-            }
-            all_cached = false;
-            double best = 1e300;
-            int best_epb = -1;
-            for (int i = 0; i < semh::kNumVariants; ++i) {
-                const semh::VariantDef v = semh::kVariants[i];
-                if (v.nq != oc.nq || !variant_ok(p.dtype, nt, v.nq, v.epb))
-                    continue;
-                for (OrderChoice& o : p.orders)
-                    if (o.nq == oc.nq)
-                        o.epb = v.epb;
-                double us = 0.0;
-                sem_status st = time_candidate(p, oc.nq, s, &us);
-                if (st != SEM_OK)
-                    return st;
-                if (log_enabled())
-                    fprintf(stderr, "[semvol] autotune %s nt=%d nq=%d epb=%d: %.2f us\n",
-                            p.dtype == SEM_F64 ? "f64" : "f32", nt, v.nq, v.epb, us);
-                if (us < best) {
-                    best = us;
-                    best_epb = v.epb;
-                }
-            }
-            if (best_epb < 0)
-                return fail(SEM_ERR_UNSUPPORTED, "no batch tile shape for Nq = %d", oc.nq);
-            oc.epb = best_epb;
-            oc.us = best;
-            total += best;
-            cache[key] = {best_epb, best};
+        std::vector<int> caps;
+        for (int i = 0; i < semh::kNumVariants; ++i) {
+            const semh::VariantDef v = semh::kVariants[i];
+            bool used = false;
+            for (const OrderChoice& o : p.orders)
+                used |= o.nq == v.nq;
+            if (used && variant_ok(p.dtype, nt, v.nq, v.epb, v.lay, p.rk))
+                caps.push_back(shape_lds(p.dtype, nt, v.nq, v.epb, v.lay));
         }
-        if (total < best_total) {
-            best_total = total;
-            best_nt = nt;
-            best_orders = chosen;
+        std::sort(caps.begin(), caps.end());
+        caps.erase(std::unique(caps.begin(), caps.end()), caps.end());
+        for (int cap : caps) {
+            std::vector<OrderChoice> chosen = p.orders;
+            double total = 0.0;
+            bool feasible = true;
+            for (OrderChoice& oc : chosen) {
+                const std::string key = cache_key(arch, p.dtype, p.rk, nt, cap, oc.nq, oc.elements);
+                auto it = cache.find(key);
+                if (it != cache.end() &&
+                    variant_ok(p.dtype, nt, oc.nq, it->second.epb, it->second.lay, p.rk) &&
+                    shape_lds(p.dtype, nt, oc.nq, it->second.epb, it->second.lay) <= cap) {
+                    oc.epb = it->second.epb;
+                    oc.lay = it->second.lay;
+                    oc.us = it->second.us;
+                    total += oc.us;
+                    continue;
+                }
+                double best = 1e300;
+                int best_epb = -1, best_lay = 0;
+                for (int i = 0; i < semh::kNumVariants; ++i) {
+                    const semh::VariantDef v = semh::kVariants[i];
+                    if (v.nq != oc.nq || !variant_ok(p.dtype, nt, v.nq, v.epb, v.lay, p.rk) ||
+                        shape_lds(p.dtype, nt, v.nq, v.epb, v.lay) > cap)
+                        continue;
+                    all_cached = false;
+                    for (OrderChoice& o : p.orders)
+                        if (o.nq == oc.nq) {
+                            o.epb = v.epb;
+                            o.lay = v.lay;
+                        }
+                    double us = 0.0;
+                    SEM_TRY(time_candidate(p, oc.nq, cap, s, &us));
+                    if (log_enabled())
+                        fprintf(stderr, "[semvol] autotune %s nt=%d lds<=%d nq=%d epb=%d layout=%d: %.2f us\n",
+                                p.dtype == SEM_F64 ? "f64" : "f32", nt, cap, v.nq, v.epb, v.lay, us);
+                    if (us < best) {
+                        best = us;
+                        best_epb = v.epb;
+                        best_lay = v.lay;
+                    }
+                }
+                if (best_epb < 0) {
+                    feasible = false;
+                    break;
+                }
+                oc.epb = best_epb;
+                oc.lay = best_lay;
+                oc.us = best;
+                total += best;
+                cache[key] = CacheEntry{best_epb, best_lay, best};
+            }
+            if (feasible && total < best_total) {
+                best_total = total;
+                best_nt = nt;
+                best_cap = cap;
+                best_orders = chosen;
+            }
         }
     }
+    if (best_orders.empty())
+        return fail(SEM_ERR_UNSUPPORTED, "no batch tile shape fits every order of the plan");
     p.nt = best_nt;
     p.orders = best_orders;
     p.autotuned = true;
@@ -677,13 +753,38 @@ sem_status autotune(PlanCore& p, bool use_cache, hipStream_t s)
         cache_write(path, merged);
     }
     if (log_enabled())
-        fprintf(stderr, "[semvol] autotune chose nt=%d (sum of per-order times %.2f us)%s\n", p.nt,
-                best_total, all_cached ? " from cache" : "");
+        fprintf(stderr, "[semvol] autotune chose nt=%d, LDS cap %d B (sum of per-order times %.2f us)%s\n",
+                p.nt, best_cap, best_total, all_cached ? " from cache" : "");
     return SEM_OK;
 }
 
+// Built-in batch shapes (no autotuning): the smallest workgroup size among
+// 256, 512 and 1024 for which every order has its single-order default tile
+// (all fluxes in LDS, else one direction at a time).
+sem_status default_shapes(PlanCore& p)
+{
+    for (int nt : semh::kBatchThreads) {
+        bool all = true;
+        for (OrderChoice& o : p.orders) {
+            o.epb = default_epb(o.nq);
+            if (variant_ok(p.dtype, nt, o.nq, o.epb, semk::FULL, p.rk))
+                o.lay = semk::FULL;
+            else if (variant_ok(p.dtype, nt, o.nq, o.epb, semk::ALIAS, p.rk))
+                o.lay = semk::ALIAS;
+            else
+                all = false;
+        }
+        if (all) {
+            p.nt = nt;
+            return SEM_OK;
+        }
+    }
+    return fail(SEM_ERR_UNSUPPORTED, "no default batch shape covers every order of the plan");
+}
+
 sem_status build_plan(const sem_block* blocks, int32_t nblocks, sem_dtype dt, const sem_phys* phys,
-                      uint32_t flags, hipStream_t s, const PlanCore* template_plan, PlanCore** out)
+                      uint32_t flags, hipStream_t s, const PlanCore* template_plan,
+                      const semk::RkStage* rk, const void* const* rk_x, PlanCore** out)
 {
     SEM_TRY(check_dtype(dt));
     if (!out)
@@ -701,6 +802,11 @@ sem_status build_plan(const sem_block* blocks, int32_t nblocks, sem_dtype dt, co
     p->dtype = dt;
     p->phys = to_phys(phys);
     p->blocks.assign(blocks, blocks + nblocks);
+    if (rk) {
+        p->rk = true;
+        p->rk_stage = *rk;
+        p->rk_x.assign(rk_x, rk_x + nblocks);
+    }
     hipError_t err = hipGetDevice(&p->device);
     if (err == hipSuccess)
         err = dt == SEM_F64 ? semh::batch_prepare<double>() : semh::batch_prepare<float>();
@@ -718,7 +824,6 @@ sem_status build_plan(const sem_block* blocks, int32_t nblocks, sem_dtype dt, co
         if (!found) {
             OrderChoice o;
             o.nq = blocks[i].Nq;
-            o.epb = default_epb(o.nq);
             o.elements = blocks[i].Ne;
             p->orders.push_back(o);
         }
@@ -734,10 +839,7 @@ sem_status build_plan(const sem_block* blocks, int32_t nblocks, sem_dtype dt, co
     } else if (flags & SEM_PLAN_AUTOTUNE) {
         st = autotune(*p, (flags & SEM_PLAN_USE_CACHE) != 0, s);
     } else {
-        p->nt = 256;
-        for (OrderChoice& o : p->orders)
-            if (!variant_ok(dt, p->nt, o.nq, o.epb))
-                st = fail(SEM_ERR_UNSUPPORTED, "no default batch shape for Nq = %d", o.nq);
+        st = default_shapes(*p);
     }
     if (st == SEM_OK)
         st = finalize(*p, s);
@@ -765,7 +867,7 @@ extern "C" sem_status sem_batch_plan(const sem_block* blocks, int32_t nblocks, s
     *out = nullptr;
     PlanCore* core = nullptr;
     SEM_TRY(build_plan(blocks, nblocks, dtype, phys, flags, static_cast<hipStream_t>(stream), nullptr,
-                       &core));
+                       nullptr, nullptr, &core));
     sem_plan p = new (std::nothrow) sem_plan_s();
     if (!p) {
         free_core(core);
@@ -792,29 +894,38 @@ extern "C" sem_status sem_batch_execute(sem_plan plan, void* stream)
     return SEM_OK;
 }
 
-extern "C" sem_status sem_plan_describe(sem_plan plan, char* buf, int32_t len)
+namespace {
+std::string describe(const PlanCore& c)
 {
-    if (!plan || !buf || len < 1)
-        return fail(SEM_ERR_INVALID_ARG, "NULL plan or buffer");
-    const PlanCore& c = plan->core;
     std::string s = "{\"dtype\": \"";
     s += c.dtype == SEM_F64 ? "f64" : "f32";
     char tmp[256];
     snprintf(tmp, sizeof tmp,
              "\", \"threads\": %d, \"grid\": %d, \"lds_bytes\": %d, \"tiles\": %d, "
-             "\"blocks\": %zu, \"autotuned\": %s, \"from_cache\": %s, \"orders\": [",
-             c.nt, c.grid, c.lds_bytes, c.ntiles, c.blocks.size(), c.autotuned ? "true" : "false",
-             c.from_cache ? "true" : "false");
+             "\"blocks\": %zu, \"fused_rk_stage\": %s, \"autotuned\": %s, \"from_cache\": %s, "
+             "\"orders\": [",
+             c.nt, c.grid, c.lds_bytes, c.ntiles, c.blocks.size(), c.rk ? "true" : "false",
+             c.autotuned ? "true" : "false", c.from_cache ? "true" : "false");
     s += tmp;
     for (size_t i = 0; i < c.orders.size(); ++i) {
-        snprintf(tmp, sizeof tmp, "%s{\"Nq\": %d, \"elems_per_block\": %d, \"elements\": %lld, "
-                                  "\"tuned_us\": %.3f}",
-                 i ? ", " : "", c.orders[i].nq, c.orders[i].epb, (long long)c.orders[i].elements,
+        snprintf(tmp, sizeof tmp,
+                 "%s{\"Nq\": %d, \"elems_per_block\": %d, \"layout\": \"%s\", \"elements\": %lld, "
+                 "\"tuned_us\": %.3f}",
+                 i ? ", " : "", c.orders[i].nq, c.orders[i].epb,
+                 c.orders[i].lay == semk::ALIAS ? "alias" : "full", (long long)c.orders[i].elements,
                  c.orders[i].us);
         s += tmp;
     }
     s += "]}";
-    snprintf(buf, (size_t)len, "%s", s.c_str());
+    return s;
+}
+}  // namespace
+
+extern "C" sem_status sem_plan_describe(sem_plan plan, char* buf, int32_t len)
+{
+    if (!plan || !buf || len < 1)
+        return fail(SEM_ERR_INVALID_ARG, "NULL plan or buffer");
+    snprintf(buf, (size_t)len, "%s", describe(plan->core).c_str());
     return SEM_OK;
 }
 
@@ -832,6 +943,7 @@ extern "C" sem_status sem_plan_destroy(sem_plan plan)
 // ===========================================================================
 struct sem_rk3_s {
     PlanCore stage[3];
+    bool fused = true;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -856,10 +968,19 @@ extern "C" sem_status sem_rk3_graph_create(const sem_block* blocks, int32_t nblo
         return fail(SEM_ERR_INVALID_ARG, "need at least one block");
     if (!std::isfinite(dt))
         return fail(SEM_ERR_INVALID_ARG, "dt is not finite");
+    const bool fused = (flags & SEM_RK3_SEPARATE_STAGES) == 0;
+    // Shu-Osher coefficients: stage k writes a_k q_n + b_k (q_k + dt v(q_k))
+    const double a[3] = {0.0, 0.75, 1.0 / 3.0};
+    const double b[3] = {1.0, 0.25, 2.0 / 3.0};
+    char* qin[3] = {static_cast<char*>(q_n), static_cast<char*>(q_1), static_cast<char*>(q_2)};
+    char* qout[3] = {static_cast<char*>(q_1), static_cast<char*>(q_2), static_cast<char*>(q_n)};
     // every block's q inside q_n and its rhs inside L at the same offset
-    std::vector<sem_block> b1(blocks, blocks + nblocks), b2(blocks, blocks + nblocks);
+    std::vector<sem_block> sb[3];
+    std::vector<const void*> xs(nblocks);
     const char* qn = static_cast<const char*>(q_n);
     const char* lb = static_cast<const char*>(L);
+    for (int k = 0; k < 3; ++k)
+        sb[k].assign(blocks, blocks + nblocks);
     for (int i = 0; i < nblocks; ++i) {
         const int64_t m = (int64_t)blocks[i].Nq * blocks[i].Nq * blocks[i].Nq;
         const int64_t bytes = (int64_t)blocks[i].Ne * 5 * m * (int64_t)es;
@@ -870,53 +991,48 @@ extern "C" sem_status sem_rk3_graph_create(const sem_block* blocks, int32_t nblo
         if (roff != off)
             return fail(SEM_ERR_INVALID_ARG, "block %d: rhs is not at the same offset in L as q in q_n",
                         i);
-        b1[i].q = static_cast<const char*>(q_1) + off;
-        b2[i].q = static_cast<const char*>(q_2) + off;
+        xs[i] = qn + off;
+        for (int k = 0; k < 3; ++k) {
+            sb[k][i].q = qin[k] + off;
+            if (fused)
+                sb[k][i].rhs = qout[k] + off;   // the fused stage writes q_{k+1} directly
+        }
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     sem_rk3 g = new (std::nothrow) sem_rk3_s();
     if (!g)
         return fail(SEM_ERR_NO_MEMORY, "graph allocation");
-    PlanCore* c0 = nullptr;
-    PlanCore* c1 = nullptr;
-    PlanCore* c2 = nullptr;
-    sem_status st = build_plan(blocks, nblocks, dtype, phys, flags, s, nullptr, &c0);
-    if (st == SEM_OK)
-        st = build_plan(b1.data(), nblocks, dtype, phys, 0, s, c0, &c1);
-    if (st == SEM_OK)
-        st = build_plan(b2.data(), nblocks, dtype, phys, 0, s, c0, &c2);
-    auto cleanup = [&]() {
-        for (PlanCore* c : {c0, c1, c2})
-            if (c) {
-                free_core(c);
-                delete c;
-            }
-    };
+    g->fused = fused;
+    PlanCore* c[3] = {nullptr, nullptr, nullptr};
+    sem_status st = SEM_OK;
+    for (int k = 0; k < 3 && st == SEM_OK; ++k) {
+        const semk::RkStage rk{a[k], b[k], dt};
+        st = build_plan(sb[k].data(), nblocks, dtype, phys, k == 0 ? flags : 0, s,
+                        k == 0 ? nullptr : c[0], fused ? &rk : nullptr, fused ? xs.data() : nullptr,
+                        &c[k]);
+    }
     if (st != SEM_OK) {
-        cleanup();
+        for (PlanCore* ck : c)
+            if (ck) {
+                free_core(ck);
+                delete ck;
+            }
         delete g;
         return st;
     }
-    g->stage[0] = *c0;
-    g->stage[1] = *c1;
-    g->stage[2] = *c2;
-    delete c0;
-    delete c1;
-    delete c2;
+    for (int k = 0; k < 3; ++k) {
+        g->stage[k] = *c[k];
+        delete c[k];
+    }
     auto destroy_all = [&]() {
-        for (PlanCore& c : g->stage)
-            free_core(&c);
+        for (PlanCore& ck : g->stage)
+            free_core(&ck);
         if (g->exec)
             (void)hipGraphExecDestroy(g->exec);
         if (g->graph)
             (void)hipGraphDestroy(g->graph);
         delete g;
     };
-    // Shu-Osher coefficients: stage s writes a_s q_n + b_s (q_s + dt L)
-    const double a[3] = {0.0, 0.75, 1.0 / 3.0};
-    const double b[3] = {1.0, 0.25, 2.0 / 3.0};
-    void* qin[3] = {q_n, q_1, q_2};
-    void* qout[3] = {q_1, q_2, q_n};
     hipStream_t cs = nullptr;
     hipError_t err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
     if (err != hipSuccess) {
@@ -925,19 +1041,19 @@ extern "C" sem_status sem_rk3_graph_create(const sem_block* blocks, int32_t nblo
     }
     err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     for (int k = 0; k < 3 && err == hipSuccess; ++k) {
-        const PlanCore& c = g->stage[k];
-        err = launch(c, c.d_tiles, c.ntiles, c.grid, c.lds_bytes, cs);
-        if (err == hipSuccess) {
+        const PlanCore& ck = g->stage[k];
+        err = launch(ck, ck.d_tiles, ck.ntiles, ck.grid, ck.lds_bytes, cs);
+        if (err == hipSuccess && !fused) {
             if (dtype == SEM_F64)
                 err = semh::launch_axpby<double>(n, a[k], static_cast<const double*>(q_n), b[k],
-                                                 static_cast<const double*>(qin[k]), dt,
+                                                 reinterpret_cast<const double*>(qin[k]), dt,
                                                  static_cast<const double*>(L),
-                                                 static_cast<double*>(qout[k]), cs);
+                                                 reinterpret_cast<double*>(qout[k]), cs);
             else
                 err = semh::launch_axpby<float>(n, a[k], static_cast<const float*>(q_n), b[k],
-                                                static_cast<const float*>(qin[k]), dt,
+                                                reinterpret_cast<const float*>(qin[k]), dt,
                                                 static_cast<const float*>(L),
-                                                static_cast<float*>(qout[k]), cs);
+                                                reinterpret_cast<float*>(qout[k]), cs);
         }
     }
     hipGraph_t graph = nullptr;
@@ -963,6 +1079,16 @@ extern "C" sem_status sem_rk3_graph_launch(sem_rk3 step, void* stream)
     hipError_t err = hipGraphLaunch(step->exec, static_cast<hipStream_t>(stream));
     if (err != hipSuccess)
         return hip_fail(err, "hipGraphLaunch");
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_rk3_graph_describe(sem_rk3 step, char* buf, int32_t len)
+{
+    if (!step || !buf || len < 1)
+        return fail(SEM_ERR_INVALID_ARG, "NULL step or buffer");
+    std::string s = std::string("{\"fused_stages\": ") + (step->fused ? "true" : "false") +
+                    ", \"stage_plan\": " + describe(step->stage[0]) + "}";
+    snprintf(buf, (size_t)len, "%s", s.c_str());
     return SEM_OK;
 }
 

@@ -36,6 +36,13 @@ struct BlockPtrs {
     const double* theta_ref; // nullable (then the full pressure is used)
     T* rhs;
     int64_t Ne;
+    const T* rk_x;           // fused Runge-Kutta stage only: x of out = a x + b (q + dt v)
+};
+
+// Stage update of an explicit Runge-Kutta method fused into the epilogue of
+// the volume term: out = a*x + b*(q + dt*v(q)), x not read when a == 0.
+struct RkStage {
+    double a, b, dt;
 };
 
 // ---------------------------------------------------------------------------
@@ -116,36 +123,174 @@ struct Shape {
     }
 };
 
-// A thread that handles more than one node of a tile keeps 1/J and the
+// Tile layouts.  FULL keeps the contravariant fluxes of all three
+// directions of every node in LDS (15 values per node, one barrier);
+// ALIAS keeps one direction at a time (5 values per node) and walks r, s, t
+// in three LDS phases, trading barriers for a third of the LDS, which lets
+// large elements (Nq >= 9) and the worst-case shape of a mixed-order batch
+// keep more workgroups resident.
+enum Layout : int { FULL = 0, ALIAS = 1 };
+
+// A thread of a FULL tile that handles more than one node keeps 1/J and the
 // gravity source of its nodes in LDS (two extra values per node) instead of
-// register arrays, so that its node loop need not be unrolled.
-template <typename T, int NQ, int EPB, int NT>
+// register arrays, so that its node loop need not be unrolled.  ALIAS tiles
+// keep each node's state in registers and allow at most two nodes per thread.
+template <typename T, int NQ, int EPB, int NT, int LAY>
 constexpr int volume_tile_values_per_node()
 {
+    if (LAY == ALIAS)
+        return 5;
     return (EPB * Shape<NQ>::M + NT - 1) / NT > 1 ? 17 : 15;
 }
 
+template <int NQ, int EPB, int NT>
+constexpr int nodes_per_thread()
+{
+    return (EPB * Shape<NQ>::M + NT - 1) / NT;
+}
+
 // LDS bytes a forward tile needs: D plus the staged values of every node.
-template <typename T, int NQ, int EPB, int NT>
+template <typename T, int NQ, int EPB, int NT, int LAY>
 constexpr int volume_tile_lds_bytes()
 {
     return (Shape<NQ>::template d_slots<T>() +
-            EPB * volume_tile_values_per_node<T, NQ, EPB, NT>() * Shape<NQ>::M) *
+            EPB * volume_tile_values_per_node<T, NQ, EPB, NT, LAY>() * Shape<NQ>::M) *
            (int)sizeof(T);
+}
+
+// Values the fused Runge-Kutta epilogue needs at its node, loaded with the
+// rest of the node's inputs in phase 1 so that no memory round trip is left
+// for the end of the tile: the stage input q and, when a != 0, x.
+template <typename T, bool RK>
+struct RkNode {
+    __device__ __forceinline__ void load(const BlockPtrs<T>&, const RkStage&, int64_t, int, int) {}
+};
+
+template <typename T>
+struct RkNode<T, true> {
+    T q[5];
+    T x[5];
+    __device__ __forceinline__ void load(const BlockPtrs<T>& B, const RkStage& rk, int64_t e, int m,
+                                         int M)
+    {
+        const T* qe = B.q + e * (5 * M) + m;
+#pragma unroll
+        for (int b = 0; b < 5; ++b)
+            q[b] = qe[b * M];
+        if (rk.a != 0.0) {
+            const T* xe = B.rk_x + e * (5 * M) + m;
+#pragma unroll
+            for (int b = 0; b < 5; ++b)
+                x[b] = xe[b * M];
+        } else {
+#pragma unroll
+            for (int b = 0; b < 5; ++b)
+                x[b] = (T)0;
+        }
+    }
+};
+
+// Epilogue for one node: rhs = -(1/J) acc + source (+ rhs when ACC), or the
+// fused Runge-Kutta stage out = a x + b (q + dt v) when RK.
+template <typename T, int M, bool ACC, bool RK>
+__device__ __forceinline__ void store_node(const BlockPtrs<T>& B, const RkStage& rk, int64_t e,
+                                           int m, const T (&acc)[5], T jinv, T src,
+                                           const RkNode<T, RK>& rn)
+{
+    T* __restrict__ re = B.rhs + e * (5 * M) + m;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        T v = -jinv * acc[b];
+        if (b == 3)
+            v += src;
+        if constexpr (RK) {
+            re[b * M] = (T)rk.a * rn.x[b] + (T)rk.b * (rn.q[b] + (T)rk.dt * v);
+        } else {
+            if constexpr (ACC)
+                v += re[b * M];
+            re[b * M] = v;
+        }
+    }
+}
+
+// Pointwise part for one node: pressure (perturbation when a reference is
+// given), 1/rho, metric terms, 1/J and the gravity source.
+template <typename T>
+struct NodeState {
+    T U1, U2, U3, Th, rinv, pp, jinv, src;
+    T g[9];
+};
+
+template <typename T, int M>
+__device__ __forceinline__ void load_node(const BlockPtrs<T>& B, const Phys& ph, int64_t e, int m,
+                                          NodeState<T>& st)
+{
+    const T* __restrict__ qe = B.q + e * (5 * M) + m;
+    const T* __restrict__ ge = B.geo + e * (10 * M) + m;
+    const T rho = qe[0];
+    st.U1 = qe[M];
+    st.U2 = qe[2 * M];
+    st.U3 = qe[3 * M];
+    st.Th = qe[4 * M];
+#pragma unroll
+    for (int s = 0; s < 9; ++s)
+        st.g[s] = ge[s * M];
+    st.jinv = ge[9 * M];
+    const bool has_ref = B.theta_ref != nullptr;
+    T rr = (T)0;
+    double thr = 0.0;
+    if (has_ref) {
+        rr = B.rho_ref[e * M + m];
+        thr = B.theta_ref[e * M + m];
+    }
+    st.src = -(T)ph.grav * (rho - rr);
+    st.pp = Pressure<T>::eval(st.Th, has_ref, thr, ph);
+    st.rinv = (T)1 / rho;
+}
+
+// Contravariant flux of direction d (sum_a g_ad f_a) of one node into LDS:
+// F[0], F[M], ..., F[4M] for the fields rho, U1, U2, U3, Theta.
+template <typename T, int M>
+__device__ __forceinline__ void put_flux(const NodeState<T>& st, int d, T* __restrict__ F)
+{
+    const T g1 = st.g[3 * d], g2 = st.g[3 * d + 1], g3 = st.g[3 * d + 2];
+    const T Ud = g1 * st.U1 + g2 * st.U2 + g3 * st.U3;   // contravariant momentum
+    const T vd = Ud * st.rinv;
+    F[0] = Ud;
+    F[M] = st.U1 * vd + g1 * st.pp;
+    F[2 * M] = st.U2 * vd + g2 * st.pp;
+    F[3 * M] = st.U3 * vd + g3 * st.pp;
+    F[4 * M] = st.Th * vd;
+}
+
+// acc[b] += sum_n D[row][n] F_b(base + n*stride), b = 0..4, out of LDS.
+template <typename T, int NQ, int M>
+__device__ __forceinline__ void contract(const T* __restrict__ sD, const T* __restrict__ F, int row,
+                                         int stride, T (&acc)[5])
+{
+#pragma unroll 2
+    for (int n = 0; n < NQ; ++n) {
+        const T dn = sD[row * NQ + n];
+#pragma unroll
+        for (int b = 0; b < 5; ++b)
+            acc[b] += dn * F[b * M + n * stride];
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Forward tile: EPB elements starting at e0, of which the first ne exist.
 // ---------------------------------------------------------------------------
-template <typename T, int NQ, int EPB, int NT, bool ACC>
-__device__ __forceinline__ void volume_tile(const BlockPtrs<T>& B, int64_t e0, int ne,
-                                            const Phys& ph, T* __restrict__ smem)
+template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK>
+__device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t e0, int ne,
+                                                 const Phys& ph, const RkStage& rk,
+                                                 T* __restrict__ smem)
 {
     constexpr int NQ2 = Shape<NQ>::NQ2;
     constexpr int M = Shape<NQ>::M;
     constexpr int NODES = EPB * M;
-    constexpr int NPT = (NODES + NT - 1) / NT;
-    constexpr int VPN = volume_tile_values_per_node<T, NQ, EPB, NT>();
+    constexpr int NPT = nodes_per_thread<NQ, EPB, NT>();
+    constexpr int VPN = volume_tile_values_per_node<T, NQ, EPB, NT, FULL>();
+    static_assert(!RK || NPT == 1, "a fused Runge-Kutta stage needs one node per thread");
     T* __restrict__ sD = smem;
     T* __restrict__ sF = smem + Shape<NQ>::template d_slots<T>();
     const int tid = threadIdx.x;
@@ -153,49 +298,23 @@ __device__ __forceinline__ void volume_tile(const BlockPtrs<T>& B, int64_t e0, i
     for (int x = tid; x < NQ2; x += NT)
         sD[x] = B.D[x];
 
-    const bool has_ref = B.theta_ref != nullptr;
-    const T grav = (T)ph.grav;
-
-    // Phase 1 for tile node t: pointwise pressure and contravariant fluxes
-    // of the three directions into LDS; returns 1/J and the source.
+    RkNode<T, RK> rn;
+    // phase 1 for tile node t: pointwise work and the three directions'
+    // fluxes into LDS; returns 1/J and the source
     auto phase1 = [&](int t, T& jinv, T& src) {
         const int es = t / M;
         const int m = t - es * M;
-        const int64_t e = e0 + es;
-        const T* __restrict__ qe = B.q + e * (5 * M) + m;
-        const T* __restrict__ ge = B.geo + e * (10 * M) + m;
-        const T rho = qe[0], U1 = qe[M], U2 = qe[2 * M], U3 = qe[3 * M], Th = qe[4 * M];
-        T g[9];
-#pragma unroll
-        for (int s = 0; s < 9; ++s)
-            g[s] = ge[s * M];
-        jinv = ge[9 * M];
-        T rr = (T)0;
-        double thr = 0.0;
-        if (has_ref) {
-            rr = B.rho_ref[e * M + m];
-            thr = B.theta_ref[e * M + m];
-        }
-        src = -grav * (rho - rr);
-        const T pp = Pressure<T>::eval(Th, has_ref, thr, ph);
-        const T rinv = (T)1 / rho;
+        NodeState<T> st;
+        load_node<T, M>(B, ph, e0 + es, m, st);
+        rn.load(B, rk, e0 + es, m, M);
         T* __restrict__ F = sF + es * (VPN * M) + m;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const T g1 = g[3 * d], g2 = g[3 * d + 1], g3 = g[3 * d + 2];
-            const T Ud = g1 * U1 + g2 * U2 + g3 * U3;   // contravariant momentum
-            const T vd = Ud * rinv;
-            T* Fd = F + d * (5 * M);
-            Fd[0] = Ud;
-            Fd[M] = U1 * vd + g1 * pp;
-            Fd[2 * M] = U2 * vd + g2 * pp;
-            Fd[3 * M] = U3 * vd + g3 * pp;
-            Fd[4 * M] = Th * vd;
-        }
+        for (int d = 0; d < 3; ++d)
+            put_flux<T, M>(st, d, F + d * (5 * M));
+        jinv = st.jinv;
+        src = st.src;
     };
-
-    // Phase 2 for tile node t: D along r, s, t out of LDS, then
-    // rhs = -(1/J) * sum + source, written once.
+    // phase 2 for tile node t: D along r (stride 1), s (Nq), t (Nq^2)
     auto phase2 = [&](int t, T jinv, T src) {
         const int es = t / M;
         const int m = t - es * M;
@@ -204,47 +323,10 @@ __device__ __forceinline__ void volume_tile(const BlockPtrs<T>& B, int64_t e0, i
         const int k = m / NQ2;
         const T* __restrict__ Fe = sF + es * (VPN * M);
         T acc[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
-        {   // r: sum_n D[i][n] F^r(n, j, k)
-            const T* Fr = Fe + NQ * j + NQ2 * k;
-#pragma unroll 2
-            for (int n = 0; n < NQ; ++n) {
-                const T dn = sD[i * NQ + n];
-#pragma unroll
-                for (int b = 0; b < 5; ++b)
-                    acc[b] += dn * Fr[b * M + n];
-            }
-        }
-        {   // s: sum_n D[j][n] F^s(i, n, k)
-            const T* Fs = Fe + 5 * M + i + NQ2 * k;
-#pragma unroll 2
-            for (int n = 0; n < NQ; ++n) {
-                const T dn = sD[j * NQ + n];
-#pragma unroll
-                for (int b = 0; b < 5; ++b)
-                    acc[b] += dn * Fs[b * M + NQ * n];
-            }
-        }
-        {   // t: sum_n D[k][n] F^t(i, j, n)
-            const T* Ft = Fe + 10 * M + i + NQ * j;
-#pragma unroll 2
-            for (int n = 0; n < NQ; ++n) {
-                const T dn = sD[k * NQ + n];
-#pragma unroll
-                for (int b = 0; b < 5; ++b)
-                    acc[b] += dn * Ft[b * M + NQ2 * n];
-            }
-        }
-        const int64_t e = e0 + es;
-        T* __restrict__ re = B.rhs + e * (5 * M) + m;
-#pragma unroll
-        for (int b = 0; b < 5; ++b) {
-            T v = -jinv * acc[b];
-            if (b == 3)
-                v += src;
-            if constexpr (ACC)
-                v += re[b * M];
-            re[b * M] = v;
-        }
+        contract<T, NQ, M>(sD, Fe + NQ * j + NQ2 * k, i, 1, acc);
+        contract<T, NQ, M>(sD, Fe + 5 * M + i + NQ2 * k, j, NQ, acc);
+        contract<T, NQ, M>(sD, Fe + 10 * M + i + NQ * j, k, NQ2, acc);
+        store_node<T, M, ACC, RK>(B, rk, e0 + es, m, acc, jinv, src, rn);
     };
 
     if constexpr (NPT == 1) {
@@ -278,6 +360,92 @@ __device__ __forceinline__ void volume_tile(const BlockPtrs<T>& B, int64_t e0, i
         }
     }
     __syncthreads();   // the LDS tile is reused by the next tile of a persistent workgroup
+}
+
+template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK>
+__device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t e0, int ne,
+                                                  const Phys& ph, const RkStage& rk,
+                                                  T* __restrict__ smem)
+{
+    constexpr int NQ2 = Shape<NQ>::NQ2;
+    constexpr int M = Shape<NQ>::M;
+    constexpr int NODES = EPB * M;
+    constexpr int NPT = nodes_per_thread<NQ, EPB, NT>();
+    static_assert(NPT <= 2, "ALIAS tiles keep at most two nodes per thread in registers");
+    static_assert(!RK || NPT == 1, "a fused Runge-Kutta stage needs one node per thread");
+    T* __restrict__ sD = smem;
+    T* __restrict__ sF = smem + Shape<NQ>::template d_slots<T>();
+    const int tid = threadIdx.x;
+
+    for (int x = tid; x < NQ2; x += NT)
+        sD[x] = B.D[x];
+
+    NodeState<T> st[NPT];
+    RkNode<T, RK> rn[NPT];
+    T acc[NPT][5];
+    bool live[NPT];
+#pragma unroll
+    for (int p = 0; p < NPT; ++p) {
+        const int t = tid + p * NT;
+        live[p] = t < NODES && t / M < ne;
+#pragma unroll
+        for (int b = 0; b < 5; ++b)
+            acc[p][b] = (T)0;
+        if (live[p]) {
+            const int es = t / M;
+            load_node<T, M>(B, ph, e0 + es, t - es * M, st[p]);
+            rn[p].load(B, rk, e0 + es, t - es * M, M);
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (d > 0)
+            __syncthreads();   // every read of the previous direction is done
+#pragma unroll
+        for (int p = 0; p < NPT; ++p)
+            if (live[p]) {
+                const int t = tid + p * NT;
+                const int es = t / M;
+                put_flux<T, M>(st[p], d, sF + es * (5 * M) + (t - es * M));
+            }
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < NPT; ++p)
+            if (live[p]) {
+                const int t = tid + p * NT;
+                const int es = t / M;
+                const int m = t - es * M;
+                const int i = m % NQ;
+                const int j = (m / NQ) % NQ;
+                const int k = m / NQ2;
+                const T* Fe = sF + es * (5 * M);
+                if (d == 0)
+                    contract<T, NQ, M>(sD, Fe + NQ * j + NQ2 * k, i, 1, acc[p]);
+                else if (d == 1)
+                    contract<T, NQ, M>(sD, Fe + i + NQ2 * k, j, NQ, acc[p]);
+                else
+                    contract<T, NQ, M>(sD, Fe + i + NQ * j, k, NQ2, acc[p]);
+            }
+    }
+#pragma unroll
+    for (int p = 0; p < NPT; ++p)
+        if (live[p]) {
+            const int t = tid + p * NT;
+            const int es = t / M;
+            store_node<T, M, ACC, RK>(B, rk, e0 + es, t - es * M, acc[p], st[p].jinv, st[p].src,
+                                      rn[p]);
+        }
+    __syncthreads();   // the LDS tile is reused by the next tile of a persistent workgroup
+}
+
+template <typename T, int NQ, int EPB, int NT, int LAY, bool ACC, bool RK>
+__device__ __forceinline__ void volume_tile(const BlockPtrs<T>& B, int64_t e0, int ne,
+                                            const Phys& ph, const RkStage& rk, T* __restrict__ smem)
+{
+    if constexpr (LAY == ALIAS)
+        volume_tile_alias<T, NQ, EPB, NT, ACC, RK>(B, e0, ne, ph, rk, smem);
+    else
+        volume_tile_full<T, NQ, EPB, NT, ACC, RK>(B, e0, ne, ph, rk, smem);
 }
 
 // ---------------------------------------------------------------------------

@@ -6,45 +6,47 @@
 
 #include "sem_device.hpp"
 
-// Compiled tile shapes (Nq, elements per workgroup).  The single-order
-// kernels use ceil64(EPB * Nq^3) threads (one node per thread); the
-// persistent batch kernel runs every shape with a fixed workgroup size.
-#define SEM_VARIANTS(X)                                   \
-    X(2, 8) X(2, 16) X(2, 32) X(2, 64) X(2, 128)          \
-    X(3, 4) X(3, 8) X(3, 16) X(3, 32)                     \
-    X(4, 1) X(4, 2) X(4, 4) X(4, 8) X(4, 16)              \
-    X(5, 1) X(5, 2) X(5, 4) X(5, 8)                       \
-    X(6, 1) X(6, 2) X(6, 4)                               \
-    X(7, 1) X(7, 2)                                       \
-    X(8, 1) X(8, 2)                                       \
-    X(9, 1)                                               \
-    X(10, 1)
+// Compiled tile shapes (Nq, elements per workgroup, layout).  The
+// single-order kernels use ceil64(EPB * Nq^3) threads (one node per thread);
+// the persistent batch kernel runs every shape with a fixed workgroup size.
+// Layout 0 keeps all three directions' fluxes in LDS, layout 1 one direction
+// at a time.
+#define SEM_VARIANTS(X)                                                        \
+    X(2, 8, 0) X(2, 16, 0) X(2, 32, 0) X(2, 64, 0) X(2, 128, 0)                \
+    X(3, 4, 0) X(3, 8, 0) X(3, 16, 0) X(3, 32, 0)                              \
+    X(4, 1, 0) X(4, 2, 0) X(4, 4, 0) X(4, 8, 0) X(4, 16, 0)                    \
+    X(5, 1, 0) X(5, 2, 0) X(5, 4, 0) X(5, 8, 0)                                \
+    X(6, 1, 0) X(6, 2, 0) X(6, 4, 0) X(6, 2, 1) X(6, 4, 1)                     \
+    X(7, 1, 0) X(7, 2, 0) X(7, 1, 1) X(7, 2, 1)                                \
+    X(8, 1, 0) X(8, 2, 0) X(8, 1, 1) X(8, 2, 1)                                \
+    X(9, 1, 0) X(9, 1, 1)                                                      \
+    X(10, 1, 0) X(10, 1, 1)
 
 namespace semh {
 
 struct VariantDef {
-    int nq, epb;
+    int nq, epb, lay;
 };
-#define SEM_X_DEF(NQ_, EPB_) VariantDef{NQ_, EPB_},
+#define SEM_X_DEF(NQ_, EPB_, LAY_) VariantDef{NQ_, EPB_, LAY_},
 inline constexpr VariantDef kVariants[] = {SEM_VARIANTS(SEM_X_DEF)};
 #undef SEM_X_DEF
 inline constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 
-constexpr int variant_index(int nq, int epb)
+constexpr int variant_index(int nq, int epb, int lay)
 {
     for (int i = 0; i < kNumVariants; ++i)
-        if (kVariants[i].nq == nq && kVariants[i].epb == epb)
+        if (kVariants[i].nq == nq && kVariants[i].epb == epb && kVariants[i].lay == lay)
             return i;
     return -1;
 }
 
 constexpr int kMaxLdsBytes = 160 * 1024;   // LDS per CU on gfx950
-constexpr int kBatchThreads[] = {256, 512};
+constexpr int kBatchThreads[] = {256, 512, 1024};
 
 // Single-order forward/adjoint launchers (defined per dtype in kernels_*.hip).
 template <typename T>
-hipError_t launch_volume(int nq, int epb, const semk::BlockPtrs<T>& B, const semk::Phys& ph,
-                         int accumulate, hipStream_t s);
+hipError_t launch_volume(int nq, int epb, int lay, const semk::BlockPtrs<T>& B,
+                         const semk::Phys& ph, int accumulate, hipStream_t s);
 template <typename T>
 hipError_t launch_adjoint(int nq, int epb, const semk::AdjPtrs<T>& B, const semk::Phys& ph,
                           int accumulate, hipStream_t s);
@@ -60,15 +62,18 @@ struct Tile {
     int32_t pad;
     int64_t e0;
 };
+// rk: the shape must also run a fused Runge-Kutta stage (one node per thread)
 template <typename T>
-bool batch_variant_ok(int nt, int nq, int epb);
+bool batch_variant_ok(int nt, int nq, int epb, int lay, bool rk);
 template <typename T>
-int batch_lds_bytes(int nt, int nq, int epb);
+int batch_lds_bytes(int nt, int nq, int epb, int lay);
+// rk == nullptr: rhs = v(q); otherwise the fused stage out = a x + b (q + dt v).
 template <typename T>
 hipError_t launch_batch(int nt, const Tile* d_tiles, int ntiles, const semk::BlockPtrs<T>* d_blocks,
-                        const semk::Phys& ph, int grid, int lds_bytes, hipStream_t s);
+                        const semk::Phys& ph, const semk::RkStage* rk, int grid, int lds_bytes,
+                        hipStream_t s);
 template <typename T>
-hipError_t batch_blocks_per_cu(int nt, int lds_bytes, int* out);
+hipError_t batch_blocks_per_cu(int nt, int lds_bytes, bool rk, int* out);
 // Must run once per process before occupancy queries or launches (sets the
 // dynamic-LDS limit of the batch kernels).
 template <typename T>

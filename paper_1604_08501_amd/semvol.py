@@ -24,14 +24,16 @@ LIB_PATH = os.path.join(_PKG, "libsem.so")
 
 SEM_OK, SEM_ERR_INVALID_ARG, SEM_ERR_UNSUPPORTED, SEM_ERR_HIP, SEM_ERR_NO_MEMORY = 0, -1, -2, -3, -4
 SEM_F64, SEM_F32 = 0, 1
-SEM_PLAN_AUTOTUNE, SEM_PLAN_USE_CACHE = 1, 2
+SEM_PLAN_AUTOTUNE, SEM_PLAN_USE_CACHE, SEM_RK3_SEPARATE_STAGES = 1, 2, 4
+SEM_LAYOUT_DEFAULT, SEM_LAYOUT_FULL, SEM_LAYOUT_ALIAS = 0, 1, 2
+LAYOUTS = {"default": SEM_LAYOUT_DEFAULT, "full": SEM_LAYOUT_FULL, "alias": SEM_LAYOUT_ALIAS}
 
 # every symbol include/sem.h declares
 EXPORTS = (
     "sem_last_error", "sem_version", "sem_tile_options", "sem_volume_rhs", "sem_volume_rhs_tiled",
     "sem_volume_rhs_adjoint", "sem_axpby", "sem_batch_plan", "sem_batch_execute",
     "sem_plan_describe", "sem_plan_destroy", "sem_rk3_graph_create", "sem_rk3_graph_launch",
-    "sem_rk3_graph_destroy",
+    "sem_rk3_graph_describe", "sem_rk3_graph_destroy",
 )
 
 
@@ -47,7 +49,7 @@ class sem_phys(ctypes.Structure):
 
 
 class sem_tile(ctypes.Structure):
-    _fields_ = [("elems_per_block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+    _fields_ = [("elems_per_block", ctypes.c_int32), ("layout", ctypes.c_int32)]
 
 
 class sem_block(ctypes.Structure):
@@ -72,7 +74,7 @@ def lib() -> ctypes.CDLL:
     sig = {
         "sem_last_error": ([], ctypes.c_char_p),
         "sem_version": ([], ctypes.c_char_p),
-        "sem_tile_options": ([i32, i32, P(i32), i32], i32),
+        "sem_tile_options": ([i32, i32, P(sem_tile), i32], i32),
         "sem_volume_rhs": ([i32, i32, i32, vp, vp, vp, vp, vp, P(sem_phys), vp, i32, vp], i32),
         "sem_volume_rhs_tiled": ([i32, i32, i32, vp, vp, vp, vp, vp, P(sem_phys), vp, i32,
                                   P(sem_tile), vp], i32),
@@ -85,6 +87,7 @@ def lib() -> ctypes.CDLL:
         "sem_rk3_graph_create": ([P(sem_block), i32, i32, P(sem_phys), u32, vp, vp, vp, vp, i64, d,
                                   vp, P(vp)], i32),
         "sem_rk3_graph_launch": ([vp, vp], i32),
+        "sem_rk3_graph_describe": ([vp, ctypes.c_char_p, i32], i32),
         "sem_rk3_graph_destroy": ([vp], i32),
     }
     for name, (args, res) in sig.items():
@@ -105,9 +108,12 @@ def version() -> str:
 
 
 def tile_options(dtype: torch.dtype, Nq: int):
-    buf = (ctypes.c_int32 * 32)()
-    n = lib().sem_tile_options(_code(dtype), Nq, buf, 32)
-    return [buf[i] for i in range(min(n, 32))]
+    """Compiled single-order tile shapes for (dtype, Nq) as
+    ``[(elems_per_block, "full" | "alias"), ...]``."""
+    buf = (sem_tile * 64)()
+    n = lib().sem_tile_options(_code(dtype), Nq, buf, 64)
+    names = {SEM_LAYOUT_FULL: "full", SEM_LAYOUT_ALIAS: "alias"}
+    return [(buf[i].elems_per_block, names[buf[i].layout]) for i in range(min(n, 64))]
 
 
 def _code(dtype: torch.dtype) -> int:
@@ -158,9 +164,11 @@ def _shape(q: torch.Tensor, D: torch.Tensor):
 
 
 def volume_rhs(q, geo, D, rho_ref=None, theta_ref=None, phys=None, out=None, accumulate=False,
-               elems_per_block: int = 0, stream=None) -> torch.Tensor:
+               elems_per_block: int = 0, layout: str = "default", stream=None) -> torch.Tensor:
     """Volume term of Eq. (volterm) plus the gravity source (``rhs = v(q)``,
-    or ``out += v(q)`` with ``accumulate``)."""
+    or ``out += v(q)`` with ``accumulate``).  ``elems_per_block``/``layout``
+    pick a compiled tile shape (see :func:`tile_options`); every shape
+    computes the same values."""
     Ne, Nq = _shape(q, D)
     M = Nq ** 3
     dt = q.dtype
@@ -171,7 +179,9 @@ def volume_rhs(q, geo, D, rho_ref=None, theta_ref=None, phys=None, out=None, acc
             _dev(theta_ref, "theta_ref", torch.float64, (Ne, M)))
     o = _dev(out, "out", dt, q.shape)
     ph = _phys(phys)
-    tile = sem_tile(int(elems_per_block), 0)
+    if layout not in LAYOUTS:
+        raise ValueError(f"layout must be one of {sorted(LAYOUTS)}")
+    tile = sem_tile(int(elems_per_block), LAYOUTS[layout])
     _check(lib().sem_volume_rhs_tiled(Ne, Nq, _code(dt), *args, ctypes.byref(ph), o,
                                       int(bool(accumulate)), ctypes.byref(tile), _stream(stream)))
     return out
@@ -282,10 +292,13 @@ class RK3Graph:
 
     ``q_n``, ``q_1``, ``q_2``, ``L`` are flat buffers of equal length; every
     block's ``q`` is a view into ``q_n`` and its ``rhs`` the view at the same
-    offset in ``L``.  ``step()`` advances ``q_n`` in place by ``dt``."""
+    offset in ``L``.  ``step()`` advances ``q_n`` in place by ``dt``.  By
+    default each stage is one launch whose epilogue writes the stage update;
+    ``separate_stages=True`` writes the rate into ``L`` and applies an axpby."""
 
     def __init__(self, blocks: Sequence[dict], q_n, q_1, q_2, L, dt: float, phys=None,
-                 autotune: bool = False, use_cache: bool = False, stream=None):
+                 autotune: bool = False, use_cache: bool = False, separate_stages: bool = False,
+                 stream=None):
         self.dtype = q_n.dtype
         arr, self._keep = _blocks(blocks, self.dtype)
         self._bufs = (q_n, q_1, q_2, L)
@@ -295,7 +308,8 @@ class RK3Graph:
             if t.numel() != n:
                 raise ValueError(f"{nm} has {t.numel()} values, expected {n}")
         self._phys = _phys(phys)
-        flags = (SEM_PLAN_AUTOTUNE if autotune else 0) | (SEM_PLAN_USE_CACHE if use_cache else 0)
+        flags = ((SEM_PLAN_AUTOTUNE if autotune else 0) | (SEM_PLAN_USE_CACHE if use_cache else 0)
+                 | (SEM_RK3_SEPARATE_STAGES if separate_stages else 0))
         h = ctypes.c_void_p()
         _check(lib().sem_rk3_graph_create(arr, len(blocks), _code(self.dtype),
                                           ctypes.byref(self._phys), flags, q_n.data_ptr(),
@@ -305,6 +319,11 @@ class RK3Graph:
 
     def step(self, stream=None) -> None:
         _check(lib().sem_rk3_graph_launch(self._h, _stream(stream)))
+
+    def describe(self) -> dict:
+        buf = ctypes.create_string_buffer(8192)
+        _check(lib().sem_rk3_graph_describe(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
 
     def close(self) -> None:
         if getattr(self, "_h", None) and self._h.value:

@@ -46,13 +46,17 @@ def test_version(L):
 
 
 def test_tile_options(L, sv):
-    buf = (ctypes.c_int32 * 16)()
+    buf = (sv.sem_tile * 16)()
     for nq in range(2, 11):
         n = L.sem_tile_options(sv.SEM_F64, nq, buf, 16)
         assert n >= 1
-        assert all(buf[i] >= 1 for i in range(n))
+        assert all(buf[i].elems_per_block >= 1 for i in range(n))
+        assert all(buf[i].layout in (sv.SEM_LAYOUT_FULL, sv.SEM_LAYOUT_ALIAS) for i in range(n))
+        assert (buf[0].elems_per_block, buf[0].layout) != (0, 0)
     assert L.sem_tile_options(sv.SEM_F64, 11, buf, 16) == 0
     assert L.sem_tile_options(7, 8, buf, 16) == 0
+    # large orders have an aliased-LDS shape
+    assert ("alias" in [lay for _, lay in sv.tile_options(__import__("torch").float64, 10)])
 
 
 # fake, suitably aligned device addresses: validation must fail before use
@@ -83,11 +87,13 @@ def test_volume_rhs_validation(L, sv, kw, status):
 
 def test_tiled_rejects_uncompiled_shape(L, sv):
     ph = sv.sem_phys(1e5, 1.4, 287.0, 9.81)
-    tile = sv.sem_tile(3, 0)
-    st = L.sem_volume_rhs_tiled(4, 8, 0, A, 2 * A, 3 * A, None, None, ctypes.byref(ph), 4 * A, 0,
-                                ctypes.byref(tile), None)
-    assert st == sv.SEM_ERR_UNSUPPORTED
-    assert b"elems_per_block" in L.sem_last_error()
+    for tile, status in ((sv.sem_tile(3, 0), sv.SEM_ERR_UNSUPPORTED),
+                         (sv.sem_tile(1, sv.SEM_LAYOUT_ALIAS), sv.SEM_ERR_UNSUPPORTED),  # Nq = 4
+                         (sv.sem_tile(1, 9), sv.SEM_ERR_INVALID_ARG)):
+        st = L.sem_volume_rhs_tiled(4, 4, 0, A, 2 * A, 3 * A, None, None, ctypes.byref(ph), 4 * A, 0,
+                                    ctypes.byref(tile), None)
+        assert st == status
+        assert b"tile" in L.sem_last_error() or b"layout" in L.sem_last_error()
 
 
 def test_adjoint_validation(L, sv):
@@ -141,6 +147,8 @@ def test_rk3_validation(L, sv):
                                   0, 1e-3, None, ctypes.byref(out)) == -1
     assert L.sem_rk3_graph_launch(None, None) == -1
     assert L.sem_rk3_graph_destroy(None) == -1
+    buf = ctypes.create_string_buffer(16)
+    assert L.sem_rk3_graph_describe(None, buf, 16) == -1
 
 
 def test_binding_fails_loudly_without_library(monkeypatch):

@@ -34,12 +34,14 @@ def host(t):
     return t.cpu().numpy()
 
 
-def run_fwd(sv, w, dtype=torch.float64, epb=0, with_ref=True, out=None, accumulate=False):
+def run_fwd(sv, w, dtype=torch.float64, epb=0, with_ref=True, out=None, accumulate=False,
+            layout="default"):
     cast = (lambda a: a) if dtype == torch.float64 else (lambda a: np.asarray(a, np.float32))
     rr = dev(cast(w.rho_ref)) if with_ref else None
     tr = dev(w.theta_ref) if with_ref else None
     return sv.volume_rhs(dev(cast(w.q)), dev(cast(w.geo)), dev(cast(w.D)), rr, tr,
-                         w.phys.as_tuple(), out=out, accumulate=accumulate, elems_per_block=epb)
+                         w.phys.as_tuple(), out=out, accumulate=accumulate, elems_per_block=epb,
+                         layout=layout)
 
 
 def oracle_fwd(oracle_mod, w, with_ref=True):
@@ -65,12 +67,18 @@ def test_affine_n4_fp64(sv, oracle_mod):
 def test_all_orders_all_tiles_fp64(sv, oracle_mod, Nq):
     opts = sv.tile_options(torch.float64, Nq)
     assert opts
-    Ne = 3 * max(opts) + 1                      # several tiles and a ragged tail
+    Ne = 3 * max(e for e, _ in opts) + 1        # several tiles and a ragged tail
     w = I.warped_workload(N=Nq - 1, n_elements=Ne, k=10 + Nq)
     ref = oracle_fwd(oracle_mod, w)
-    for epb in opts:
-        e = err(host(run_fwd(sv, w, epb=epb)), ref)
-        assert e.max() <= TOL64, (Nq, epb, e)
+    for epb, lay in opts:
+        e = err(host(run_fwd(sv, w, epb=epb, layout=lay)), ref)
+        assert e.max() <= TOL64, (Nq, epb, lay, e)
+    # accumulate through every shape
+    base = np.random.default_rng(Nq).standard_normal(w.q.shape)
+    for epb, lay in opts:
+        out = dev(base.copy())
+        run_fwd(sv, w, epb=epb, layout=lay, out=out, accumulate=True)
+        assert err(host(out), base + ref).max() <= TOL64, (Nq, epb, lay)
 
 
 @pytest.mark.parametrize("Nq", [2, 5, 8, 10])
@@ -78,9 +86,9 @@ def test_all_orders_fp32(sv, oracle_mod, Nq):
     w = I.warped_workload(N=Nq - 1, n_elements=37, k=20 + Nq)
     w32 = I.to_fp32(w)
     ref = oracle_fwd(oracle_mod, I.upcast(w32))
-    for epb in sv.tile_options(torch.float32, Nq):
-        e = err(host(run_fwd(sv, w32, torch.float32, epb=epb)), ref)
-        assert e.max() <= TOL32, (Nq, epb, e)
+    for epb, lay in sv.tile_options(torch.float32, Nq):
+        e = err(host(run_fwd(sv, w32, torch.float32, epb=epb, layout=lay)), ref)
+        assert e.max() <= TOL32, (Nq, epb, lay, e)
 
 
 def test_without_reference_and_accumulate(sv, oracle_mod):
@@ -255,7 +263,8 @@ def test_batch_mixed_order(sv, oracle_mod, dtype, autotune):
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_rk3_graph(sv, oracle_mod, dtype):
+@pytest.mark.parametrize("separate", [False, True])
+def test_rk3_graph(sv, oracle_mod, dtype, separate):
     ws = I.mixed_order_workloads(orders=(2, 4, 6), per_order=40, k=80)
     cast = (lambda a: a) if dtype == torch.float64 else (lambda a: np.asarray(a, np.float32))
     sizes = [w.q.size for w in ws]
@@ -270,7 +279,8 @@ def test_rk3_graph(sv, oracle_mod, dtype):
                            theta_ref=dev(w.theta_ref), rhs=L[off:off + sz].view(w.q.shape)))
         off += sz
     dt = 1e-3
-    g = sv.RK3Graph(blocks, q_n, q_1, q_2, L, dt, ws[0].phys.as_tuple())
+    g = sv.RK3Graph(blocks, q_n, q_1, q_2, L, dt, ws[0].phys.as_tuple(), separate_stages=separate)
+    assert g.describe()["fused_stages"] == (not separate)
 
     # oracle: one SSP-RK3 step of each block (blocks are independent)
     def oracle_step():
