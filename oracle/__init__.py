@@ -55,6 +55,9 @@ def _load():
     i64 = ctypes.c_int64
     lib.sem_oracle_volume_rhs.argtypes = [i64, i64, i32, p, p, p, p, p, d, d, d, d, p, i32]
     lib.sem_oracle_volume_rhs.restype = None
+    lib.sem_oracle_volume_rhs_ext.argtypes = [i64, i64, i32, i32, ctypes.c_uint32, p, p, p, p, p,
+                                              d, d, d, d, p, i32]
+    lib.sem_oracle_volume_rhs_ext.restype = None
     lib.sem_oracle_volume_rhs_adjoint.argtypes = [i64, i64, i32, p, p, p, d, d, d, d, p, p, i32]
     lib.sem_oracle_volume_rhs_adjoint.restype = None
     lib.sem_oracle_max_threads.restype = ctypes.c_int
@@ -102,6 +105,33 @@ def volume_rhs(D, geo, q, rho_ref=None, theta_ref=None, phys=(1e5, 1.4, 287.0, 9
     p0, gamma, R, grav = phys
     lib.sem_oracle_volume_rhs(e0, e1, Nq, _ptr(D), _ptr(geo), _ptr(q), _ptr(rho_ref),
                               _ptr(theta_ref), p0, gamma, R, grav, _ptr(out), int(bool(accumulate)))
+    return out
+
+
+DIR_R, DIR_S, DIR_T = 1, 2, 4
+
+
+def volume_rhs_ext(D, geo, q, rho_ref=None, theta_ref=None, phys=(1e5, 1.4, 287.0, 9.81),
+                   dirs=DIR_R | DIR_S | DIR_T, out=None, accumulate=False, elements=None):
+    """Volume term with 5 or 8 fields (``q`` shaped ``[Ne, nf, Nq^3]``; fields 5-7
+    are passive tracers) and a subset ``dirs`` of the reference directions
+    (bit 0 r, bit 1 s, bit 2 t; the paper's benchmark kernel uses r and s)."""
+    lib = _load()
+    D, geo, q = _f64(D), _f64(geo), _f64(q)
+    rho_ref, theta_ref = _f64(rho_ref), _f64(theta_ref)
+    if (rho_ref is None) != (theta_ref is None):
+        raise ValueError("rho_ref and theta_ref must both be given or both be None")
+    Ne, nf, M = q.shape
+    Nq = D.shape[0]
+    assert nf in (5, 8) and M == Nq ** 3 and geo.shape == (Ne, 10, M)
+    if out is None:
+        out = np.zeros_like(q)
+    assert out.dtype == np.float64 and out.flags.c_contiguous and out.shape == q.shape
+    e0, e1 = (0, Ne) if elements is None else elements
+    p0, gamma, R, grav = phys
+    lib.sem_oracle_volume_rhs_ext(e0, e1, Nq, nf, int(dirs), _ptr(D), _ptr(geo), _ptr(q),
+                                  _ptr(rho_ref), _ptr(theta_ref), p0, gamma, R, grav, _ptr(out),
+                                  int(bool(accumulate)))
     return out
 
 

@@ -46,11 +46,13 @@ static double eos_pressure(double theta, double p0, double gamma, double R)
     return p0 * pow(R * theta / p0, gamma);
 }
 
-/* Flux column f_a(q) of equation set 2C (Sec. 2), restricted to the five
- * prognostic fields: f[a][b] for direction a = 0..2 and field b = 0..4,
+/* Flux column f_a(q) of equation set 2C (Sec. 2): f[a][b] for direction
+ * a = 0..2 and field b < nf, with nf = 5 (rho, U1, U2, U3, Theta) or 8 (plus
+ * the passive tracers Q1, Q2, Q3):
  *   f_a = [U_a, U_a U_1/rho + delta_a1 p, U_a U_2/rho + delta_a2 p,
- *          U_a U_3/rho + delta_a3 p, U_a Theta/rho]. */
-static void physical_flux(const double qn[5], double p, double f[3][5])
+ *          U_a U_3/rho + delta_a3 p, U_a Theta/rho, U_a Q_i/rho]. */
+#define MAXF 8
+static void physical_flux(const double* qn, int nf, double p, double f[3][MAXF])
 {
     const double rho = qn[0];
     for (int a = 0; a < 3; ++a) {
@@ -58,7 +60,8 @@ static void physical_flux(const double qn[5], double p, double f[3][5])
         f[a][0] = Ua;
         for (int c = 0; c < 3; ++c)
             f[a][1 + c] = Ua * qn[1 + c] / rho + (a == c ? p : 0.0);
-        f[a][4] = Ua * qn[4] / rho;
+        for (int b = 4; b < nf; ++b)
+            f[a][b] = Ua * qn[b] / rho;
     }
 }
 
@@ -115,43 +118,47 @@ void sem_oracle_set_threads(int n)
  *                                          + D[j][n] g_a2(i,n,k) f_ab(i,n,k)
  *                                          + D[k][n] g_a3(i,j,n) f_ab(i,j,n) ]
  *   v_U3 += -grav * (rho - rho_ref)
- * Elements [e0, e1) are evaluated; rhs is indexed like q (element e at
- * rhs + e*5*Nq^3).  accumulate != 0 adds to rhs instead of overwriting.
+ * for nf = 5 or 8 fields (q, rhs [e][nf][Nq^3]).  `dirs` selects which of the
+ * three sums enter (bit 0 = r, bit 1 = s, bit 2 = t): the paper's benchmark
+ * kernel fuses the r and s terms only (dirs = 3).  Elements [e0, e1) are
+ * evaluated; rhs is indexed like q.  accumulate != 0 adds to rhs instead of
+ * overwriting (the listed kernels' rhsq update).
  */
-void sem_oracle_volume_rhs(int64_t e0, int64_t e1, int32_t Nq, const double* D,
-                           const double* geo, const double* q,
-                           const double* rho_ref, const double* theta_ref,
-                           double p0, double gamma, double R, double grav,
-                           double* rhs, int32_t accumulate)
+void sem_oracle_volume_rhs_ext(int64_t e0, int64_t e1, int32_t Nq, int32_t nf, uint32_t dirs,
+                               const double* D, const double* geo, const double* q,
+                               const double* rho_ref, const double* theta_ref,
+                               double p0, double gamma, double R, double grav,
+                               double* rhs, int32_t accumulate)
 {
     const int64_t M = (int64_t)Nq * Nq * Nq;
+    const int use_r = (dirs & 1u) != 0, use_s = (dirs & 2u) != 0, use_t = (dirs & 4u) != 0;
 #pragma omp parallel
     {
-        double* f = (double*)malloc(sizeof(double) * (size_t)M * 15);
+        double* f = (double*)malloc(sizeof(double) * (size_t)M * 3 * MAXF);
 #pragma omp for schedule(static)
         for (int64_t e = e0; e < e1; ++e) {
-            const double* qe = q + e * 5 * M;
+            const double* qe = q + e * nf * M;
             const double* ge = geo + e * 10 * M;
-            double* re = rhs + e * 5 * M;
+            double* re = rhs + e * nf * M;
             /* pointwise: pressure (perturbation if a reference is given) and
              * the physical flux at every node, stored f[m][a][b] */
             for (int64_t m = 0; m < M; ++m) {
-                double qn[5];
-                for (int b = 0; b < 5; ++b)
+                double qn[MAXF];
+                for (int b = 0; b < nf; ++b)
                     qn[b] = qe[b * M + m];
                 double p = eos_pressure(qn[4], p0, gamma, R);
                 if (theta_ref)
                     p -= eos_pressure(theta_ref[e * M + m], p0, gamma, R);
-                physical_flux(qn, p, (double(*)[5])(f + m * 15));
+                physical_flux(qn, nf, p, (double(*)[MAXF])(f + m * 3 * MAXF));
             }
 #define G(a, d, node) ge[(3 * (d) + (a)) * M + (node)]
-#define F(node, a, b) f[(node) * 15 + (a) * 5 + (b)]
+#define F(node, a, b) f[(node) * 3 * MAXF + (a) * MAXF + (b)]
             for (int k = 0; k < Nq; ++k)
                 for (int j = 0; j < Nq; ++j)
                     for (int i = 0; i < Nq; ++i) {
                         const int64_t m = i + (int64_t)Nq * j + (int64_t)Nq * Nq * k;
                         const double Jinv = ge[9 * M + m];
-                        for (int b = 0; b < 5; ++b) {
+                        for (int b = 0; b < nf; ++b) {
                             double sr = 0.0, ss = 0.0, st = 0.0;
                             for (int n = 0; n < Nq; ++n)
                                 for (int a = 0; a < 3; ++a) {
@@ -162,7 +169,8 @@ void sem_oracle_volume_rhs(int64_t e0, int64_t e1, int32_t Nq, const double* D,
                                     ss += D[j * Nq + n] * G(a, 1, ns) * F(ns, a, b);
                                     st += D[k * Nq + n] * G(a, 2, nt) * F(nt, a, b);
                                 }
-                            double v = -Jinv * (sr + ss + st);
+                            double v = -Jinv * ((use_r ? sr : 0.0) + (use_s ? ss : 0.0) +
+                                                (use_t ? st : 0.0));
                             if (b == 3) {
                                 const double rr = rho_ref ? rho_ref[e * M + m] : 0.0;
                                 v += -grav * (qe[m] - rr);
@@ -175,6 +183,18 @@ void sem_oracle_volume_rhs(int64_t e0, int64_t e1, int32_t Nq, const double* D,
         }
         free(f);
     }
+}
+
+/* The five-field volume term with all three directions (the operation the
+ * library's sem_volume_rhs computes). */
+void sem_oracle_volume_rhs(int64_t e0, int64_t e1, int32_t Nq, const double* D,
+                           const double* geo, const double* q,
+                           const double* rho_ref, const double* theta_ref,
+                           double p0, double gamma, double R, double grav,
+                           double* rhs, int32_t accumulate)
+{
+    sem_oracle_volume_rhs_ext(e0, e1, Nq, 5, 7u, D, geo, q, rho_ref, theta_ref, p0, gamma, R, grav,
+                              rhs, accumulate);
 }
 
 /*
