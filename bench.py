@@ -12,7 +12,10 @@ beside it, with its error against the FP64 oracle and the FP32/FP64 speedup.
 Beside it the line carries the mixed-order persistent batch (N = 3, 5, 7, 9,
 5000 elements each; autotuned), one SSP-RK3 step replayed from a HIP graph
 (stage updates fused into the batch launch, and as separate RHS + axpby
-launches), and the adjoint (N=7, 8192 elements), each in FP64 and FP32.
+launches), and the adjoint (N=7, 8192 elements), each in FP64 and FP32, and
+the paper-comparable configuration on the Table 2 shapes (FP32, 8 fields,
+r+s and r+s+t, Nq = 4, 8, 12, 16 at 3,538,944 nodes) with the paper's own
+timings on its hardware quoted beside it as context.
 The warm-up (30 launches by default) lets the clock settle before the timed
 launches, so the rate is the sustained one.
 
@@ -156,6 +159,49 @@ def bench_adjoint(sv, I, steps: int, warmup: int, stream):
     return out
 
 
+# The paper's Table 2 (its level-8 kernel: FP32, 8 fields, r+s, rhsq
+# accumulated) at a constant 3,538,944 nodes, for context; other hardware.
+PAPER_TABLE2_MS = {
+    4: {"R9 Fury X": 3.19944, "GTX Titan X": 1.78229, "Tesla K40c": 5.54140},
+    8: {"R9 Fury X": 1.36146, "GTX Titan X": 2.06701, "Tesla K40c": 3.28739},
+    12: {"R9 Fury X": 4.26229, "GTX Titan X": 2.20707, "Tesla K40c": 5.34723},
+    16: {"R9 Fury X": 6.45935, "GTX Titan X": 2.11778, "Tesla K40c": 5.53732},
+}
+
+
+def bench_paper_table2(sv, I, steps: int, warmup: int, stream):
+    """The paper-comparable configuration on the Table 2 shapes: 3,538,944 nodes
+    at Nq = 4, 8, 12, 16 (Ne = 55296, 6912, 2048, 864) on a warped 2:2:1 box,
+    FP32, 8 fields (3 passive tracers), the r and s terms only and with all
+    three directions, the paper's constants (p0 = 1, gamma = 1.4, R = 1, no
+    gravity, no reference state), rhs accumulated as in the listed kernels."""
+    import torch
+    phys = (1.0, 1.4, 1.0, 0.0)
+    out = {"workload": "Table 2 shapes: 3,538,944 nodes, 8 fields, FP32, rhsq += v",
+           "phys": phys}
+    for Nq in (4, 8, 12, 16):
+        w = I.to_fp32(I.table2_workload(Nq))
+        nodes = w.Ne * Nq ** 3
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        q, geo, D = t(w.q), t(w.geo), t(w.D)
+        rhs = torch.zeros_like(q)
+        row = {"Ne": w.Ne, "paper_ms": PAPER_TABLE2_MS[Nq]}
+        for name, dirs, geo_words in (("rs", 3, 7), ("rst", 7, 10)):
+            ms, _ = time_launches(lambda: sv.volume_rhs_ext(q, geo, D, None, None, phys, dirs=dirs,
+                                                            out=rhs, accumulate=True),
+                                  steps, warmup, stream)
+            # per node: q 8 + metric terms of the used directions and 1/J read,
+            # rhs 8 read and 8 written, 4 bytes each
+            byt = (8 + geo_words + 16) * 4 * nodes
+            row[name] = {"ms": ms, "el_s": w.Ne / (ms * 1e-3), "GBs": byt / (ms * 1e-3) / 1e9,
+                         "bytes": byt}
+        row["speedup_rs_vs_fury_x"] = PAPER_TABLE2_MS[Nq]["R9 Fury X"] / row["rs"]["ms"]
+        out[f"Nq{Nq}"] = row
+        del q, geo, D, rhs
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, budget_s: float):
     import oracle
     phys = w.phys.as_tuple()
@@ -285,6 +331,7 @@ def main(argv=None):
     if not a.no_extra:
         line["batch_mixed_order"] = bench_batch_and_rk3(sv, I, a.steps, a.warmup, stream)
         line["adjoint"] = bench_adjoint(sv, I, a.steps, a.warmup, stream)
+        line["paper_table2"] = bench_paper_table2(sv, I, a.steps, a.warmup, stream)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(line), flush=True)

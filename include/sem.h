@@ -134,6 +134,46 @@ sem_status sem_volume_rhs_tiled(int32_t Ne, int32_t Nq, sem_dtype dtype,
 int32_t sem_tile_options(sem_dtype dtype, int32_t Nq, sem_tile* out, int32_t cap);
 
 /*
+ * Extended volume term: the full prognostic vector of Sec. 2 with the three
+ * passive tracers Q1..Q3 (flux U_a Q_i / rho), and the choice of the reference
+ * directions that enter Eq. (volterm).  The paper's benchmark kernel fuses
+ * the r and s terms of 8 fields (nfields = 8, dirs = SEM_DIR_R | SEM_DIR_S).
+ *   nfields   5 (rho, U1, U2, U3, Theta) or 8 (plus Q1, Q2, Q3);
+ *             q, rhs: [Ne][nfields][Nq^3]
+ *   dirs      SEM_DIR_R | SEM_DIR_S, or SEM_DIR_R | SEM_DIR_S | SEM_DIR_T; the
+ *             geo slots of an excluded direction are not read
+ *   Nq        2..10, 12 or 16 (in FP64, Nq = 16 does not fit the 160 KB LDS)
+ * All other arguments, the gravity source and the reference state are as for
+ * sem_volume_rhs.  Each (Nq, nfields, dirs) has one built-in tile shape.
+ * Errors: unsupported nfields / dirs / Nq -> SEM_ERR_UNSUPPORTED; otherwise as
+ * sem_volume_rhs.  Allocates nothing.
+ */
+#define SEM_DIR_R 1u
+#define SEM_DIR_S 2u
+#define SEM_DIR_T 4u
+sem_status sem_volume_rhs_ext(int32_t Ne, int32_t Nq, sem_dtype dtype, int32_t nfields,
+                              uint32_t dirs, const void* D, const void* geo, const void* q,
+                              const void* rho_ref, const double* theta_ref,
+                              const sem_phys* phys, void* rhs, int32_t accumulate,
+                              void* stream);
+
+/*
+ * Volume term of sem_volume_rhs for affine elements, whose metric terms g and
+ * 1/J are constant in each element (Sec. 2 names them geometric factors of the
+ * reference-to-physical map; for x = A xi + b they do not vary inside the
+ * element):
+ *   geo_elem  [Ne][10], slot 3*d + a = g_{a d}, slot 9 = 1/J, one set per element
+ * Every other argument as for sem_volume_rhs; Nq 2..10, 12, 16 (FP64 Nq = 16
+ * excluded by the LDS).  The per-node metric arrays are 10 of the 22 values a
+ * node moves in FP64; this form moves 12.
+ * Errors as for sem_volume_rhs.  Allocates nothing.
+ */
+sem_status sem_volume_rhs_affine(int32_t Ne, int32_t Nq, sem_dtype dtype, const void* D,
+                                 const void* geo_elem, const void* q, const void* rho_ref,
+                                 const double* theta_ref, const sem_phys* phys, void* rhs,
+                                 int32_t accumulate, void* stream);
+
+/*
  * Vector-Jacobian product of the volume term with respect to the state
  * (derivative of the flux column and EOS of Sec. 2):
  *   mu = (dv/dq)^T lambda        (mu += ... if accumulate != 0)
@@ -154,7 +194,7 @@ sem_status sem_axpby(int64_t n, sem_dtype dtype, double a, const void* x, double
 
 /* ---------------------------------------------------------------------------
  * Mixed-order batch: many element blocks, each of one order, evaluated by ONE
- * persistent kernel launch.  A block has the layouts above with its own Nq and
+ * kernel launch (one tile of elements per workgroup).  A block has the layouts above with its own Nq and
  * Ne; every block of a plan shares dtype and phys.
  * ------------------------------------------------------------------------- */
 typedef struct sem_block {
@@ -187,7 +227,7 @@ sem_status sem_batch_plan(const sem_block* blocks, int32_t nblocks, sem_dtype dt
                           const sem_phys* phys, uint32_t flags, void* stream,
                           sem_plan* out);
 
-/* Enqueues the whole batch as one persistent launch: rhs of every block =
+/* Enqueues the whole batch as one launch: rhs of every block =
  * v(q) of that block.  Allocates nothing. */
 sem_status sem_batch_execute(sem_plan plan, void* stream);
 
@@ -203,7 +243,7 @@ sem_status sem_plan_destroy(sem_plan plan);
  * the method-of-lines rate, Sec. 2), captured once in a HIP graph:
  *   q1 = q + dt v(q);  q2 = 3/4 q + 1/4 (q1 + dt v(q1));
  *   q  = 1/3 q + 2/3 (q2 + dt v(q2))          (q updated in place)
- * By default each stage is ONE persistent batch launch whose epilogue writes
+ * By default each stage is ONE batch launch whose epilogue writes
  * the stage update directly (the rate is never stored).  With
  * SEM_RK3_SEPARATE_STAGES each stage is a batch launch writing v into L plus
  * one sem_axpby.

@@ -1,3 +1,3 @@
-// Persistent batch kernel, float instantiation.
+// Mixed-order batch kernel, float instantiation.
 #define SEM_REAL float
 #include "batch.inc"

@@ -1,3 +1,3 @@
-// Persistent batch kernel, double instantiation.
+// Mixed-order batch kernel, double instantiation.
 #define SEM_REAL double
 #include "batch.inc"

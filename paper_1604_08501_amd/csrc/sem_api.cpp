@@ -119,12 +119,11 @@ sem_status check_ptr(const void* p, size_t align, const char* name, bool require
             return _st;               \
     } while (0)
 
-sem_status check_volume_args(int32_t Ne, int32_t Nq, sem_dtype dt, const void* D, const void* geo,
-                             const void* q, const void* rho_ref, const double* theta_ref,
-                             const sem_phys* phys, const void* rhs)
+// Pointers, alignment, the reference pair and aliasing of a volume-term call.
+sem_status check_volume_ptrs(sem_dtype dt, const void* D, const void* geo, const void* q,
+                             const void* rho_ref, const double* theta_ref, const sem_phys* phys,
+                             const void* rhs)
 {
-    SEM_TRY(check_dtype(dt));
-    SEM_TRY(check_order(Ne, Nq));
     if (!phys)
         return fail(SEM_ERR_INVALID_ARG, "phys is NULL");
     const size_t es = elem_size(dt);
@@ -139,6 +138,15 @@ sem_status check_volume_args(int32_t Ne, int32_t Nq, sem_dtype dt, const void* D
     if (rhs == q || rhs == geo || rhs == D || rhs == rho_ref || rhs == (const void*)theta_ref)
         return fail(SEM_ERR_INVALID_ARG, "rhs aliases an input array");
     return SEM_OK;
+}
+
+sem_status check_volume_args(int32_t Ne, int32_t Nq, sem_dtype dt, const void* D, const void* geo,
+                             const void* q, const void* rho_ref, const double* theta_ref,
+                             const sem_phys* phys, const void* rhs)
+{
+    SEM_TRY(check_dtype(dt));
+    SEM_TRY(check_order(Ne, Nq));
+    return check_volume_ptrs(dt, D, geo, q, rho_ref, theta_ref, phys, rhs);
 }
 
 template <typename T>
@@ -216,6 +224,75 @@ extern "C" sem_status sem_volume_rhs(int32_t Ne, int32_t Nq, sem_dtype dtype, co
 {
     return sem_volume_rhs_tiled(Ne, Nq, dtype, D, geo, q, rho_ref, theta_ref, phys, rhs, accumulate,
                                 nullptr, stream);
+}
+
+extern "C" sem_status sem_volume_rhs_ext(int32_t Ne, int32_t Nq, sem_dtype dtype, int32_t nfields,
+                                         uint32_t dirs, const void* D, const void* geo,
+                                         const void* q, const void* rho_ref,
+                                         const double* theta_ref, const sem_phys* phys, void* rhs,
+                                         int32_t accumulate, void* stream)
+{
+    SEM_TRY(check_dtype(dtype));
+    if (Ne < 1)
+        return fail(SEM_ERR_INVALID_ARG, "Ne = %d: at least one element is required", Ne);
+    if (nfields != 5 && nfields != 8)
+        return fail(SEM_ERR_UNSUPPORTED, "nfields = %d (5, or 8 with the passive tracers)", nfields);
+    if (dirs != (SEM_DIR_R | SEM_DIR_S) && dirs != (SEM_DIR_R | SEM_DIR_S | SEM_DIR_T))
+        return fail(SEM_ERR_UNSUPPORTED, "dirs = %u (r+s = 3 or r+s+t = 7)", dirs);
+    const bool ok = dtype == SEM_F64 ? semh::ext_supported<double>(Nq, nfields, (int)dirs)
+                                     : semh::ext_supported<float>(Nq, nfields, (int)dirs);
+    if (!ok)
+        return fail(SEM_ERR_UNSUPPORTED,
+                    "Nq = %d with %d fields and dirs = %u is not compiled for this dtype "
+                    "(Nq 2..10, 12, 16 where the LDS allows)", Nq, nfields, dirs);
+    SEM_TRY(check_volume_ptrs(dtype, D, geo, q, rho_ref, theta_ref, phys, rhs));
+    if (nfields == 5 && dirs == 7 && Nq <= kMaxNq)
+        return sem_volume_rhs(Ne, Nq, dtype, D, geo, q, rho_ref, theta_ref, phys, rhs, accumulate,
+                              stream);
+    const semk::Phys ph = to_phys(phys);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t err;
+    if (dtype == SEM_F64)
+        err = semh::launch_volume_ext<double>(
+            Nq, nfields, (int)dirs, block_ptrs<double>(Ne, D, geo, q, rho_ref, theta_ref, rhs), ph,
+            accumulate, s);
+    else
+        err = semh::launch_volume_ext<float>(
+            Nq, nfields, (int)dirs, block_ptrs<float>(Ne, D, geo, q, rho_ref, theta_ref, rhs), ph,
+            accumulate, s);
+    if (err != hipSuccess)
+        return hip_fail(err, "extended volume kernel launch");
+    return SEM_OK;
+}
+
+extern "C" sem_status sem_volume_rhs_affine(int32_t Ne, int32_t Nq, sem_dtype dtype, const void* D,
+                                            const void* geo_elem, const void* q,
+                                            const void* rho_ref, const double* theta_ref,
+                                            const sem_phys* phys, void* rhs, int32_t accumulate,
+                                            void* stream)
+{
+    SEM_TRY(check_dtype(dtype));
+    if (Ne < 1)
+        return fail(SEM_ERR_INVALID_ARG, "Ne = %d: at least one element is required", Ne);
+    const bool ok = dtype == SEM_F64 ? semh::affine_supported<double>(Nq)
+                                     : semh::affine_supported<float>(Nq);
+    if (!ok)
+        return fail(SEM_ERR_UNSUPPORTED, "Nq = %d is not compiled for per-element metric terms "
+                                         "in this dtype (Nq 2..10, 12, 16 where the LDS allows)",
+                    Nq);
+    SEM_TRY(check_volume_ptrs(dtype, D, geo_elem, q, rho_ref, theta_ref, phys, rhs));
+    const semk::Phys ph = to_phys(phys);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t err;
+    if (dtype == SEM_F64)
+        err = semh::launch_volume_affine<double>(
+            Nq, block_ptrs<double>(Ne, D, geo_elem, q, rho_ref, theta_ref, rhs), ph, accumulate, s);
+    else
+        err = semh::launch_volume_affine<float>(
+            Nq, block_ptrs<float>(Ne, D, geo_elem, q, rho_ref, theta_ref, rhs), ph, accumulate, s);
+    if (err != hipSuccess)
+        return hip_fail(err, "affine volume kernel launch");
+    return SEM_OK;
 }
 
 extern "C" sem_status sem_volume_rhs_adjoint(int32_t Ne, int32_t Nq, sem_dtype dtype, const void* D,
@@ -301,7 +378,6 @@ struct PlanCore {
     sem_dtype dtype = SEM_F64;
     semk::Phys phys{};
     int nt = 256;
-    int grid = 0;
     int lds_bytes = 0;
     int ntiles = 0;
     int device = 0;
@@ -340,16 +416,16 @@ sem_status check_block(const sem_block& b, int idx, sem_dtype dt, const sem_phys
 }
 
 template <typename T>
-std::vector<semk::BlockPtrs<T>> host_block_table(const PlanCore& p)
+std::vector<semk::BatchBlock<T>> host_block_table(const PlanCore& p)
 {
-    std::vector<semk::BlockPtrs<T>> v;
+    std::vector<semk::BatchBlock<T>> v;
     v.reserve(p.blocks.size());
     for (size_t i = 0; i < p.blocks.size(); ++i) {
         const sem_block& b = p.blocks[i];
         semk::BlockPtrs<T> bp = block_ptrs<T>(b.Ne, b.D, b.geo, b.q, b.rho_ref, b.theta_ref, b.rhs);
         if (p.rk)
             bp.rk_x = static_cast<const T*>(p.rk_x[i]);
-        v.push_back(bp);
+        v.push_back(semk::BatchBlock<T>{bp, p.phys, p.rk_stage});
     }
     return v;
 }
@@ -421,31 +497,26 @@ hipError_t occupancy(sem_dtype dt, int nt, int lds, bool rk, int* bpc)
                          : semh::batch_blocks_per_cu<float>(nt, lds, rk, bpc);
 }
 
-hipError_t launch(const PlanCore& p, const semh::Tile* d_tiles, int ntiles, int grid, int lds,
-                  hipStream_t s)
+hipError_t launch(const PlanCore& p, const semh::Tile* d_tiles, int ntiles, int lds, hipStream_t s)
 {
-    const semk::RkStage* rk = p.rk ? &p.rk_stage : nullptr;
     if (p.dtype == SEM_F64)
         return semh::launch_batch<double>(p.nt, d_tiles, ntiles,
-                                          static_cast<const semk::BlockPtrs<double>*>(p.d_blocks),
-                                          p.phys, rk, grid, lds, s);
+                                          static_cast<const semk::BatchBlock<double>*>(p.d_blocks),
+                                          p.rk, lds, s);
     return semh::launch_batch<float>(p.nt, d_tiles, ntiles,
-                                     static_cast<const semk::BlockPtrs<float>*>(p.d_blocks), p.phys,
-                                     rk, grid, lds, s);
+                                     static_cast<const semk::BatchBlock<float>*>(p.d_blocks), p.rk,
+                                     lds, s);
 }
 
-sem_status resident_grid(const PlanCore& p, int ntiles, int lds, int* grid)
+// The batch kernel must fit at least one workgroup per CU with `lds` bytes.
+sem_status check_resident(const PlanCore& p, int lds)
 {
-    int bpc = 0, ncu = 0;
+    int bpc = 0;
     hipError_t err = occupancy(p.dtype, p.nt, lds, p.rk, &bpc);
     if (err != hipSuccess)
         return hip_fail(err, "occupancy query");
-    err = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p.device);
-    if (err != hipSuccess)
-        return hip_fail(err, "CU count query");
     if (bpc < 1)
         return fail(SEM_ERR_UNSUPPORTED, "batch kernel cannot be resident with %d B of LDS", lds);
-    *grid = std::max(1, std::min(ntiles, bpc * ncu));
     return SEM_OK;
 }
 
@@ -455,8 +526,8 @@ sem_status upload_blocks(PlanCore& p, hipStream_t s)
         (void)hipFree(p.d_blocks);
     p.d_blocks = nullptr;
     const size_t bt_bytes = p.blocks.size() *
-                            (p.dtype == SEM_F64 ? sizeof(semk::BlockPtrs<double>)
-                                                : sizeof(semk::BlockPtrs<float>));
+                            (p.dtype == SEM_F64 ? sizeof(semk::BatchBlock<double>)
+                                                : sizeof(semk::BatchBlock<float>));
     hipError_t err = hipMalloc(&p.d_blocks, bt_bytes);
     if (err != hipSuccess)
         return fail(SEM_ERR_NO_MEMORY, "plan block table (%zu B): %s", bt_bytes,
@@ -477,8 +548,8 @@ sem_status upload_blocks(PlanCore& p, hipStream_t s)
     return SEM_OK;
 }
 
-// Upload the tile table for the current choices and fix the grid from the
-// occupancy of the chosen workgroup size and LDS.
+// Upload the tile table for the current choices and check that the chosen
+// workgroup size and LDS can be resident.
 sem_status finalize(PlanCore& p, hipStream_t s)
 {
     SEM_TRY(upload_blocks(p, s));
@@ -497,7 +568,7 @@ sem_status finalize(PlanCore& p, hipStream_t s)
         err = hipStreamSynchronize(s);
     if (err != hipSuccess)
         return hip_fail(err, "upload tile table");
-    return resident_grid(p, p.ntiles, p.lds_bytes, &p.grid);
+    return check_resident(p, p.lds_bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -612,8 +683,7 @@ void cache_write(const std::string& path, const std::map<std::string, CacheEntry
 sem_status time_candidate(PlanCore& p, int nq, int cap, hipStream_t s, double* us_out)
 {
     std::vector<semh::Tile> tiles = make_tiles(p.blocks, p.orders, nq);
-    int grid = 0;
-    SEM_TRY(resident_grid(p, (int)tiles.size(), cap, &grid));
+    SEM_TRY(check_resident(p, cap));
     semh::Tile* d_t = nullptr;
     hipError_t err = hipMalloc((void**)&d_t, tiles.size() * sizeof(semh::Tile));
     if (err != hipSuccess)
@@ -628,7 +698,7 @@ sem_status time_candidate(PlanCore& p, int nq, int cap, hipStream_t s, double* u
     for (int r = 0; r < 7 && err == hipSuccess; ++r) {
         err = hipEventRecord(e0, s);
         if (err == hipSuccess)
-            err = launch(p, d_t, (int)tiles.size(), grid, cap, s);
+            err = launch(p, d_t, (int)tiles.size(), cap, s);
         if (err == hipSuccess)
             err = hipEventRecord(e1, s);
         if (err == hipSuccess)
@@ -887,8 +957,7 @@ extern "C" sem_status sem_batch_execute(sem_plan plan, void* stream)
     const PlanCore& c = plan->core;
     if (!c.d_tiles || !c.d_blocks)
         return fail(SEM_ERR_INVALID_ARG, "plan has no device tables (destroyed?)");
-    hipError_t err = launch(c, c.d_tiles, c.ntiles, c.grid, c.lds_bytes,
-                            static_cast<hipStream_t>(stream));
+    hipError_t err = launch(c, c.d_tiles, c.ntiles, c.lds_bytes, static_cast<hipStream_t>(stream));
     if (err != hipSuccess)
         return hip_fail(err, "batch kernel launch");
     return SEM_OK;
@@ -901,10 +970,10 @@ std::string describe(const PlanCore& c)
     s += c.dtype == SEM_F64 ? "f64" : "f32";
     char tmp[256];
     snprintf(tmp, sizeof tmp,
-             "\", \"threads\": %d, \"grid\": %d, \"lds_bytes\": %d, \"tiles\": %d, "
+             "\", \"threads\": %d, \"lds_bytes\": %d, \"tiles\": %d, "
              "\"blocks\": %zu, \"fused_rk_stage\": %s, \"autotuned\": %s, \"from_cache\": %s, "
              "\"orders\": [",
-             c.nt, c.grid, c.lds_bytes, c.ntiles, c.blocks.size(), c.rk ? "true" : "false",
+             c.nt, c.lds_bytes, c.ntiles, c.blocks.size(), c.rk ? "true" : "false",
              c.autotuned ? "true" : "false", c.from_cache ? "true" : "false");
     s += tmp;
     for (size_t i = 0; i < c.orders.size(); ++i) {
@@ -1042,7 +1111,7 @@ extern "C" sem_status sem_rk3_graph_create(const sem_block* blocks, int32_t nblo
     err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     for (int k = 0; k < 3 && err == hipSuccess; ++k) {
         const PlanCore& ck = g->stage[k];
-        err = launch(ck, ck.d_tiles, ck.ntiles, ck.grid, ck.lds_bytes, cs);
+        err = launch(ck, ck.d_tiles, ck.ntiles, ck.lds_bytes, cs);
         if (err == hipSuccess && !fused) {
             if (dtype == SEM_F64)
                 err = semh::launch_axpby<double>(n, a[k], static_cast<const double*>(q_n), b[k],

@@ -45,6 +45,15 @@ struct RkStage {
     double a, b, dt;
 };
 
+// Device-side descriptor of one block of a mixed-order batch launch: its
+// arrays, the physical constants and the fused stage coefficients.
+template <typename T>
+struct BatchBlock {
+    BlockPtrs<T> b;
+    Phys ph;
+    RkStage rk;
+};
+
 // ---------------------------------------------------------------------------
 // Pressure entering the flux (Sec. 2 EOS p = p0 (R Theta / p0)^gamma).
 // With a reference state it is the perturbation p - p_ref.
@@ -123,24 +132,31 @@ struct Shape {
     }
 };
 
-// Tile layouts.  FULL keeps the contravariant fluxes of all three
-// directions of every node in LDS (15 values per node, one barrier);
-// ALIAS keeps one direction at a time (5 values per node) and walks r, s, t
-// in three LDS phases, trading barriers for a third of the LDS, which lets
-// large elements (Nq >= 9) and the worst-case shape of a mixed-order batch
-// keep more workgroups resident.
+// Tile layouts.  FULL keeps the contravariant fluxes of every active
+// direction of every node in LDS (one barrier); ALIAS keeps one direction at
+// a time and walks the directions in separate LDS phases, trading barriers
+// for a fraction of the LDS, which lets large elements (Nq >= 9) and the
+// worst-case shape of a mixed-order batch keep more workgroups resident.
 enum Layout : int { FULL = 0, ALIAS = 1 };
 
-// A thread of a FULL tile that handles more than one node keeps 1/J and the
-// gravity source of its nodes in LDS (two extra values per node) instead of
-// register arrays, so that its node loop need not be unrolled.  ALIAS tiles
-// keep each node's state in registers and allow at most two nodes per thread.
-template <typename T, int NQ, int EPB, int NT, int LAY>
-constexpr int volume_tile_values_per_node()
+// Fields per node: NF = 5 (rho, U1, U2, U3, Theta) or 8 (plus the passive
+// tracers Q1..Q3, whose flux is U_a Q_i / rho).  Active reference directions:
+// bit 0 r, bit 1 s, bit 2 t (DIRS = 7 for the full volume term, 3 for the
+// paper's fused r+s benchmark kernel).
+template <int DIRS>
+constexpr int ndirs()
 {
-    if (LAY == ALIAS)
-        return 5;
-    return (EPB * Shape<NQ>::M + NT - 1) / NT > 1 ? 17 : 15;
+    return ((DIRS & 1) != 0) + ((DIRS & 2) != 0) + ((DIRS & 4) != 0);
+}
+
+// position of direction d among the active ones (its LDS slot in FULL tiles)
+template <int DIRS>
+constexpr int dir_slot(int d)
+{
+    int s = 0;
+    for (int x = 0; x < d; ++x)
+        s += (DIRS >> x) & 1;
+    return s;
 }
 
 template <int NQ, int EPB, int NT>
@@ -149,12 +165,31 @@ constexpr int nodes_per_thread()
     return (EPB * Shape<NQ>::M + NT - 1) / NT;
 }
 
+// ALIAS tiles keep each node's state in registers: at most 2 nodes per thread
+// in FP64, 4 in FP32.
+template <typename T>
+constexpr int alias_max_nodes_per_thread()
+{
+    return sizeof(T) == 4 ? 4 : 2;
+}
+
+// A thread of a FULL tile that handles more than one node keeps 1/J and the
+// gravity source of its nodes in LDS (two extra values per node) instead of
+// register arrays, so that its node loop need not be unrolled.
+template <typename T, int NQ, int EPB, int NT, int LAY, int NF = 5, int DIRS = 7>
+constexpr int volume_tile_values_per_node()
+{
+    if (LAY == ALIAS)
+        return NF;
+    return ndirs<DIRS>() * NF + (nodes_per_thread<NQ, EPB, NT>() > 1 ? 2 : 0);
+}
+
 // LDS bytes a forward tile needs: D plus the staged values of every node.
-template <typename T, int NQ, int EPB, int NT, int LAY>
+template <typename T, int NQ, int EPB, int NT, int LAY, int NF = 5, int DIRS = 7>
 constexpr int volume_tile_lds_bytes()
 {
     return (Shape<NQ>::template d_slots<T>() +
-            EPB * volume_tile_values_per_node<T, NQ, EPB, NT, LAY>() * Shape<NQ>::M) *
+            EPB * volume_tile_values_per_node<T, NQ, EPB, NT, LAY, NF, DIRS>() * Shape<NQ>::M) *
            (int)sizeof(T);
 }
 
@@ -191,15 +226,16 @@ struct RkNode<T, true> {
 };
 
 // Epilogue for one node: rhs = -(1/J) acc + source (+ rhs when ACC), or the
-// fused Runge-Kutta stage out = a x + b (q + dt v) when RK.
-template <typename T, int M, bool ACC, bool RK>
+// fused Runge-Kutta stage out = a x + b (q + dt v) when RK (five fields).
+template <typename T, int M, int NF, bool ACC, bool RK>
 __device__ __forceinline__ void store_node(const BlockPtrs<T>& B, const RkStage& rk, int64_t e,
-                                           int m, const T (&acc)[5], T jinv, T src,
+                                           int m, const T (&acc)[NF], T jinv, T src,
                                            const RkNode<T, RK>& rn)
 {
-    T* __restrict__ re = B.rhs + e * (5 * M) + m;
+    static_assert(!RK || NF == 5, "the fused Runge-Kutta stage is for the five-field state");
+    T* __restrict__ re = B.rhs + e * (NF * M) + m;
 #pragma unroll
-    for (int b = 0; b < 5; ++b) {
+    for (int b = 0; b < NF; ++b) {
         T v = -jinv * acc[b];
         if (b == 3)
             v += src;
@@ -214,28 +250,36 @@ __device__ __forceinline__ void store_node(const BlockPtrs<T>& B, const RkStage&
 }
 
 // Pointwise part for one node: pressure (perturbation when a reference is
-// given), 1/rho, metric terms, 1/J and the gravity source.
-template <typename T>
+// given), 1/rho, metric terms of the active directions, 1/J, the gravity
+// source and the tracers.
+template <typename T, int NF>
 struct NodeState {
     T U1, U2, U3, Th, rinv, pp, jinv, src;
     T g[9];
+    T Q[NF > 5 ? NF - 5 : 1];
 };
 
-template <typename T, int M>
+// GEOE: the metric terms are given once per element (affine elements,
+// geo[e][10]) instead of at every node (geo[e][10][Nq^3]).
+template <typename T, int M, int NF, int DIRS, bool GEOE = false>
 __device__ __forceinline__ void load_node(const BlockPtrs<T>& B, const Phys& ph, int64_t e, int m,
-                                          NodeState<T>& st)
+                                          NodeState<T, NF>& st)
 {
-    const T* __restrict__ qe = B.q + e * (5 * M) + m;
-    const T* __restrict__ ge = B.geo + e * (10 * M) + m;
+    const T* __restrict__ qe = B.q + e * (NF * M) + m;
+    constexpr int GS = GEOE ? 1 : M;   // stride between metric slots
+    const T* __restrict__ ge = GEOE ? B.geo + e * 10 : B.geo + e * (10 * M) + m;
     const T rho = qe[0];
     st.U1 = qe[M];
     st.U2 = qe[2 * M];
     st.U3 = qe[3 * M];
     st.Th = qe[4 * M];
 #pragma unroll
+    for (int b = 5; b < NF; ++b)
+        st.Q[b - 5] = qe[b * M];
+#pragma unroll
     for (int s = 0; s < 9; ++s)
-        st.g[s] = ge[s * M];
-    st.jinv = ge[9 * M];
+        st.g[s] = ((DIRS >> (s / 3)) & 1) ? ge[s * GS] : (T)0;
+    st.jinv = ge[9 * GS];
     const bool has_ref = B.theta_ref != nullptr;
     T rr = (T)0;
     double thr = 0.0;
@@ -249,9 +293,9 @@ __device__ __forceinline__ void load_node(const BlockPtrs<T>& B, const Phys& ph,
 }
 
 // Contravariant flux of direction d (sum_a g_ad f_a) of one node into LDS:
-// F[0], F[M], ..., F[4M] for the fields rho, U1, U2, U3, Theta.
-template <typename T, int M>
-__device__ __forceinline__ void put_flux(const NodeState<T>& st, int d, T* __restrict__ F)
+// F[b*M] for the fields b = rho, U1, U2, U3, Theta (and the tracers).
+template <typename T, int M, int NF>
+__device__ __forceinline__ void put_flux(const NodeState<T, NF>& st, int d, T* __restrict__ F)
 {
     const T g1 = st.g[3 * d], g2 = st.g[3 * d + 1], g3 = st.g[3 * d + 2];
     const T Ud = g1 * st.U1 + g2 * st.U2 + g3 * st.U3;   // contravariant momentum
@@ -261,26 +305,44 @@ __device__ __forceinline__ void put_flux(const NodeState<T>& st, int d, T* __res
     F[2 * M] = st.U2 * vd + g2 * st.pp;
     F[3 * M] = st.U3 * vd + g3 * st.pp;
     F[4 * M] = st.Th * vd;
+#pragma unroll
+    for (int b = 5; b < NF; ++b)
+        F[b * M] = st.Q[b - 5] * vd;
 }
 
-// acc[b] += sum_n D[row][n] F_b(base + n*stride), b = 0..4, out of LDS.
-template <typename T, int NQ, int M>
+// acc[b] += sum_n D[row][n] F_b(base + n*stride), b < NF, out of LDS.
+template <typename T, int NQ, int M, int NF>
 __device__ __forceinline__ void contract(const T* __restrict__ sD, const T* __restrict__ F, int row,
-                                         int stride, T (&acc)[5])
+                                         int stride, T (&acc)[NF])
 {
 #pragma unroll 2
     for (int n = 0; n < NQ; ++n) {
         const T dn = sD[row * NQ + n];
 #pragma unroll
-        for (int b = 0; b < 5; ++b)
+        for (int b = 0; b < NF; ++b)
             acc[b] += dn * F[b * M + n * stride];
     }
+}
+
+// D along direction d for the node (i, j, k): r runs over i (stride 1),
+// s over j (stride Nq), t over k (stride Nq^2).
+template <typename T, int NQ, int M, int NF>
+__device__ __forceinline__ void contract_dir(const T* __restrict__ sD, const T* __restrict__ Fd,
+                                             int d, int i, int j, int k, T (&acc)[NF])
+{
+    constexpr int NQ2 = NQ * NQ;
+    if (d == 0)
+        contract<T, NQ, M, NF>(sD, Fd + NQ * j + NQ2 * k, i, 1, acc);
+    else if (d == 1)
+        contract<T, NQ, M, NF>(sD, Fd + i + NQ2 * k, j, NQ, acc);
+    else
+        contract<T, NQ, M, NF>(sD, Fd + i + NQ * j, k, NQ2, acc);
 }
 
 // ---------------------------------------------------------------------------
 // Forward tile: EPB elements starting at e0, of which the first ne exist.
 // ---------------------------------------------------------------------------
-template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK>
+template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK, int NF, int DIRS, bool GEOE>
 __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t e0, int ne,
                                                  const Phys& ph, const RkStage& rk,
                                                  T* __restrict__ smem)
@@ -289,7 +351,8 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
     constexpr int M = Shape<NQ>::M;
     constexpr int NODES = EPB * M;
     constexpr int NPT = nodes_per_thread<NQ, EPB, NT>();
-    constexpr int VPN = volume_tile_values_per_node<T, NQ, EPB, NT, FULL>();
+    constexpr int VPN = volume_tile_values_per_node<T, NQ, EPB, NT, FULL, NF, DIRS>();
+    constexpr int SCAL = ndirs<DIRS>() * NF;   // offset of the staged 1/J and source
     static_assert(!RK || NPT == 1, "a fused Runge-Kutta stage needs one node per thread");
     T* __restrict__ sD = smem;
     T* __restrict__ sF = smem + Shape<NQ>::template d_slots<T>();
@@ -299,22 +362,23 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
         sD[x] = B.D[x];
 
     RkNode<T, RK> rn;
-    // phase 1 for tile node t: pointwise work and the three directions'
+    // phase 1 for tile node t: pointwise work and the active directions'
     // fluxes into LDS; returns 1/J and the source
     auto phase1 = [&](int t, T& jinv, T& src) {
         const int es = t / M;
         const int m = t - es * M;
-        NodeState<T> st;
-        load_node<T, M>(B, ph, e0 + es, m, st);
+        NodeState<T, NF> st;
+        load_node<T, M, NF, DIRS, GEOE>(B, ph, e0 + es, m, st);
         rn.load(B, rk, e0 + es, m, M);
         T* __restrict__ F = sF + es * (VPN * M) + m;
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-            put_flux<T, M>(st, d, F + d * (5 * M));
+            if ((DIRS >> d) & 1)
+                put_flux<T, M, NF>(st, d, F + dir_slot<DIRS>(d) * (NF * M));
         jinv = st.jinv;
         src = st.src;
     };
-    // phase 2 for tile node t: D along r (stride 1), s (Nq), t (Nq^2)
+    // phase 2 for tile node t: D along the active directions out of LDS
     auto phase2 = [&](int t, T jinv, T src) {
         const int es = t / M;
         const int m = t - es * M;
@@ -322,11 +386,15 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
         const int j = (m / NQ) % NQ;
         const int k = m / NQ2;
         const T* __restrict__ Fe = sF + es * (VPN * M);
-        T acc[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
-        contract<T, NQ, M>(sD, Fe + NQ * j + NQ2 * k, i, 1, acc);
-        contract<T, NQ, M>(sD, Fe + 5 * M + i + NQ2 * k, j, NQ, acc);
-        contract<T, NQ, M>(sD, Fe + 10 * M + i + NQ * j, k, NQ2, acc);
-        store_node<T, M, ACC, RK>(B, rk, e0 + es, m, acc, jinv, src, rn);
+        T acc[NF];
+#pragma unroll
+        for (int b = 0; b < NF; ++b)
+            acc[b] = (T)0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if ((DIRS >> d) & 1)
+                contract_dir<T, NQ, M, NF>(sD, Fe + dir_slot<DIRS>(d) * (NF * M), d, i, j, k, acc);
+        store_node<T, M, NF, ACC, RK>(B, rk, e0 + es, m, acc, jinv, src, rn);
     };
 
     if constexpr (NPT == 1) {
@@ -344,7 +412,7 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
                 T jinv, src;
                 phase1(t, jinv, src);
                 const int es = t / M;
-                T* S = sF + es * (VPN * M) + 15 * M + (t - es * M);
+                T* S = sF + es * (VPN * M) + SCAL * M + (t - es * M);
                 S[0] = jinv;
                 S[M] = src;
             }
@@ -354,15 +422,14 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
         for (int t = tid; t < NODES; t += NT) {
             if (t / M < ne) {
                 const int es = t / M;
-                const T* S = sF + es * (VPN * M) + 15 * M + (t - es * M);
+                const T* S = sF + es * (VPN * M) + SCAL * M + (t - es * M);
                 phase2(t, S[0], S[M]);
             }
         }
     }
-    __syncthreads();   // the LDS tile is reused by the next tile of a persistent workgroup
 }
 
-template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK>
+template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK, int NF, int DIRS, bool GEOE>
 __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t e0, int ne,
                                                   const Phys& ph, const RkStage& rk,
                                                   T* __restrict__ smem)
@@ -371,7 +438,8 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
     constexpr int M = Shape<NQ>::M;
     constexpr int NODES = EPB * M;
     constexpr int NPT = nodes_per_thread<NQ, EPB, NT>();
-    static_assert(NPT <= 2, "ALIAS tiles keep at most two nodes per thread in registers");
+    static_assert(NPT <= alias_max_nodes_per_thread<T>(),
+                  "ALIAS tiles keep every node's state of a thread in registers");
     static_assert(!RK || NPT == 1, "a fused Runge-Kutta stage needs one node per thread");
     T* __restrict__ sD = smem;
     T* __restrict__ sF = smem + Shape<NQ>::template d_slots<T>();
@@ -380,33 +448,35 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
     for (int x = tid; x < NQ2; x += NT)
         sD[x] = B.D[x];
 
-    NodeState<T> st[NPT];
+    NodeState<T, NF> st[NPT];
     RkNode<T, RK> rn[NPT];
-    T acc[NPT][5];
+    T acc[NPT][NF];
     bool live[NPT];
 #pragma unroll
     for (int p = 0; p < NPT; ++p) {
         const int t = tid + p * NT;
         live[p] = t < NODES && t / M < ne;
 #pragma unroll
-        for (int b = 0; b < 5; ++b)
+        for (int b = 0; b < NF; ++b)
             acc[p][b] = (T)0;
         if (live[p]) {
             const int es = t / M;
-            load_node<T, M>(B, ph, e0 + es, t - es * M, st[p]);
+            load_node<T, M, NF, DIRS, GEOE>(B, ph, e0 + es, t - es * M, st[p]);
             rn[p].load(B, rk, e0 + es, t - es * M, M);
         }
     }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        if (d > 0)
+        if (!((DIRS >> d) & 1))
+            continue;
+        if (dir_slot<DIRS>(d) > 0)
             __syncthreads();   // every read of the previous direction is done
 #pragma unroll
         for (int p = 0; p < NPT; ++p)
             if (live[p]) {
                 const int t = tid + p * NT;
                 const int es = t / M;
-                put_flux<T, M>(st[p], d, sF + es * (5 * M) + (t - es * M));
+                put_flux<T, M, NF>(st[p], d, sF + es * (NF * M) + (t - es * M));
             }
         __syncthreads();
 #pragma unroll
@@ -415,16 +485,8 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
                 const int t = tid + p * NT;
                 const int es = t / M;
                 const int m = t - es * M;
-                const int i = m % NQ;
-                const int j = (m / NQ) % NQ;
-                const int k = m / NQ2;
-                const T* Fe = sF + es * (5 * M);
-                if (d == 0)
-                    contract<T, NQ, M>(sD, Fe + NQ * j + NQ2 * k, i, 1, acc[p]);
-                else if (d == 1)
-                    contract<T, NQ, M>(sD, Fe + i + NQ2 * k, j, NQ, acc[p]);
-                else
-                    contract<T, NQ, M>(sD, Fe + i + NQ * j, k, NQ2, acc[p]);
+                contract_dir<T, NQ, M, NF>(sD, sF + es * (NF * M), d, m % NQ, (m / NQ) % NQ,
+                                           m / NQ2, acc[p]);
             }
     }
 #pragma unroll
@@ -432,20 +494,20 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
         if (live[p]) {
             const int t = tid + p * NT;
             const int es = t / M;
-            store_node<T, M, ACC, RK>(B, rk, e0 + es, t - es * M, acc[p], st[p].jinv, st[p].src,
-                                      rn[p]);
+            store_node<T, M, NF, ACC, RK>(B, rk, e0 + es, t - es * M, acc[p], st[p].jinv,
+                                          st[p].src, rn[p]);
         }
-    __syncthreads();   // the LDS tile is reused by the next tile of a persistent workgroup
 }
 
-template <typename T, int NQ, int EPB, int NT, int LAY, bool ACC, bool RK>
+template <typename T, int NQ, int EPB, int NT, int LAY, bool ACC, bool RK, int NF = 5, int DIRS = 7,
+          bool GEOE = false>
 __device__ __forceinline__ void volume_tile(const BlockPtrs<T>& B, int64_t e0, int ne,
                                             const Phys& ph, const RkStage& rk, T* __restrict__ smem)
 {
     if constexpr (LAY == ALIAS)
-        volume_tile_alias<T, NQ, EPB, NT, ACC, RK>(B, e0, ne, ph, rk, smem);
+        volume_tile_alias<T, NQ, EPB, NT, ACC, RK, NF, DIRS, GEOE>(B, e0, ne, ph, rk, smem);
     else
-        volume_tile_full<T, NQ, EPB, NT, ACC, RK>(B, e0, ne, ph, rk, smem);
+        volume_tile_full<T, NQ, EPB, NT, ACC, RK, NF, DIRS, GEOE>(B, e0, ne, ph, rk, smem);
 }
 
 // ---------------------------------------------------------------------------

@@ -8,7 +8,7 @@
 
 // Compiled tile shapes (Nq, elements per workgroup, layout).  The
 // single-order kernels use ceil64(EPB * Nq^3) threads (one node per thread);
-// the persistent batch kernel runs every shape with a fixed workgroup size.
+// the mixed-order batch kernel runs every shape with a fixed workgroup size.
 // Layout 0 keeps all three directions' fluxes in LDS, layout 1 one direction
 // at a time.
 #define SEM_VARIANTS(X)                                                        \
@@ -54,7 +54,23 @@ template <typename T>
 hipError_t launch_axpby(int64_t n, double a, const T* x, double b, const T* y, double c,
                         const T* z, T* out, hipStream_t s);
 
-// Persistent batch kernel (defined per dtype in batch_*.hip).
+// Extended volume term (defined per dtype in ext_*.hip): nf = 5 or 8 fields,
+// dirs = 3 (r+s) or 7 (r+s+t), Nq in 2..10, 12, 16 where the LDS allows.
+template <typename T>
+bool ext_supported(int nq, int nf, int dirs);
+template <typename T>
+hipError_t launch_volume_ext(int nq, int nf, int dirs, const semk::BlockPtrs<T>& B,
+                             const semk::Phys& ph, int accumulate, hipStream_t s);
+// Volume term with per-element metric terms (affine elements; geo [Ne][10]),
+// five fields, r+s+t, Nq in 2..10, 12, 16 where the LDS allows.
+template <typename T>
+bool affine_supported(int nq);
+template <typename T>
+hipError_t launch_volume_affine(int nq, const semk::BlockPtrs<T>& B, const semk::Phys& ph,
+                                int accumulate, hipStream_t s);
+
+// Mixed-order batch kernel (defined per dtype in batch_*.hip): one tile per
+// workgroup.
 struct Tile {
     int32_t block;
     int32_t variant;
@@ -67,10 +83,11 @@ template <typename T>
 bool batch_variant_ok(int nt, int nq, int epb, int lay, bool rk);
 template <typename T>
 int batch_lds_bytes(int nt, int nq, int epb, int lay);
-// rk == nullptr: rhs = v(q); otherwise the fused stage out = a x + b (q + dt v).
+// rk = false: rhs = v(q); rk = true: every block runs the fused stage
+// out = a x + b (q + dt v) with the coefficients of its descriptor.
 template <typename T>
-hipError_t launch_batch(int nt, const Tile* d_tiles, int ntiles, const semk::BlockPtrs<T>* d_blocks,
-                        const semk::Phys& ph, const semk::RkStage* rk, int grid, int lds_bytes,
+hipError_t launch_batch(int nt, const Tile* d_tiles, int ntiles,
+                        const semk::BatchBlock<T>* d_blocks, bool rk, int lds_bytes,
                         hipStream_t s);
 template <typename T>
 hipError_t batch_blocks_per_cu(int nt, int lds_bytes, bool rk, int* out);

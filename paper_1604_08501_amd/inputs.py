@@ -162,6 +162,52 @@ def _ref_coords(N: int):
     return x[m % Nq], x[(m // Nq) % Nq], x[m // (Nq * Nq)]
 
 
+def _nodal_derivative(D: np.ndarray, F: np.ndarray, d: int) -> np.ndarray:
+    """Apply the 1-D differentiation matrix along reference direction d to
+    nodal fields F[..., m] (m = i + Nq j + Nq^2 k)."""
+    Nq = D.shape[0]
+    G = F.reshape(F.shape[:-1] + (Nq, Nq, Nq))       # [..., k, j, i]
+    if d == 0:
+        out = np.einsum("in,...kjn->...kji", D, G)
+    elif d == 1:
+        out = np.einsum("jn,...kni->...kji", D, G)
+    else:
+        out = np.einsum("kn,...nji->...kji", D, G)
+    return out.reshape(F.shape)
+
+
+def curl_metric_geo(xyz: np.ndarray, N: int) -> np.ndarray:
+    """Metric terms in conservative curl form from the nodal coordinates
+    ``xyz[e][3][Nq^3]``: for cyclic (d, e, f) and cyclic (a, b, c)
+
+        g_ad = D_f (x_c D_e x_b) - D_e (x_c D_f x_b),
+
+    the discrete counterpart of J dxi_d/dx_a = (dx/dxi_e x dx/dxi_f)_a.  Since
+    the tensor-product derivatives commute, sum_d D_d g_ad = 0 holds to round-off
+    (the discrete metric identities), so a uniform state keeps a zero flux
+    divergence on curved elements.  1/J comes from the determinant of the
+    discrete Jacobian D_d x_a.
+    """
+    D = diff_matrix(N)
+    Ne, _, M = xyz.shape
+    # the curl form is unchanged by a translation of x (the derivatives
+    # commute); element-local coordinates keep the products small
+    xyz = xyz - xyz.mean(axis=2, keepdims=True)
+    dx = np.stack([_nodal_derivative(D, xyz, d) for d in range(3)], axis=-1)   # [e, a, m, d]
+    geo = np.empty((Ne, NGEO, M))
+    for d in range(3):
+        e_, f_ = (d + 1) % 3, (d + 2) % 3
+        for a in range(3):
+            b, c = (a + 1) % 3, (a + 2) % 3
+            Pe = xyz[:, c] * dx[:, b, :, e_]
+            Pf = xyz[:, c] * dx[:, b, :, f_]
+            geo[:, 3 * d + a] = _nodal_derivative(D, Pe, f_) - _nodal_derivative(D, Pf, e_)
+    A = dx.transpose(0, 2, 1, 3)                                          # [e, m, a, d]
+    _, J = _cofactor_jac(A)
+    geo[:, 9] = 1.0 / J
+    return geo
+
+
 @dataclasses.dataclass
 class Mesh:
     N: int
@@ -195,30 +241,37 @@ def affine_mesh(N: int, rng: np.random.Generator, n_side: int = 4) -> Mesh:
     return Mesh(N=N, Ne=Ne, geo=pack_geo(A), xyz=xyz, A=A, kind="affine")
 
 
-def warped_mesh(N: int, n_side: int = 32, elements: Optional[np.ndarray] = None,
-                length: float = LENGTH, warp: float = WARP) -> Mesh:
-    """Curvilinear box: ``n_side^3`` elements of the unit cube, warped by
+def warped_mesh(N: int, n_side=32, elements: Optional[np.ndarray] = None,
+                length=LENGTH, warp: float = WARP, metrics: str = "analytic") -> Mesh:
+    """Curvilinear box: ``n_side^3`` elements of the unit cube (or
+    ``nx x ny x nz`` when ``n_side`` is a triple), warped by
 
         x += w sin(pi y) sin(pi z),  y += w sin(pi z) sin(pi x),
         z += w sin(pi x) sin(pi y)
 
-    (all three applied simultaneously to the unwarped coordinates), then
-    scaled by ``length``.  Metric terms come from the analytic derivative of
-    the map at every node.  ``elements`` selects a subset of the element
-    indices ``e = ex + n(ey + n ez)`` (default: all).
+    (all three applied simultaneously to the unwarped unit-cube coordinates),
+    then scaled by ``length`` (a number, or one length per axis).  Metric terms
+    come from the analytic derivative of the map at every node.  ``elements``
+    selects a subset of the element indices ``e = ex + nx(ey + ny ez)``
+    (default: all).  ``metrics="curl"`` forms the metric terms in
+    conservative curl form from the node coordinates (see
+    :func:`curl_metric_geo`) instead of the analytic Jacobian.
     """
+    if metrics not in ("analytic", "curl"):
+        raise ValueError("metrics must be 'analytic' or 'curl'")
+    nx, ny, nz = (n_side,) * 3 if np.isscalar(n_side) else tuple(n_side)
+    Lx, Ly, Lz = (length,) * 3 if np.isscalar(length) else tuple(length)
     if elements is None:
-        elements = np.arange(n_side ** 3)
+        elements = np.arange(nx * ny * nz)
     elements = np.asarray(elements, dtype=np.int64)
     Ne = elements.size
     r, s, t = _ref_coords(N)
-    ex = elements % n_side
-    ey = (elements // n_side) % n_side
-    ez = elements // (n_side * n_side)
-    h = 1.0 / n_side
-    X = ((ex[:, None] + 0.5 * (r[None] + 1.0)) * h)
-    Y = ((ey[:, None] + 0.5 * (s[None] + 1.0)) * h)
-    Z = ((ez[:, None] + 0.5 * (t[None] + 1.0)) * h)
+    ex = elements % nx
+    ey = (elements // nx) % ny
+    ez = elements // (nx * ny)
+    X = (ex[:, None] + 0.5 * (r[None] + 1.0)) / nx
+    Y = (ey[:, None] + 0.5 * (s[None] + 1.0)) / ny
+    Z = (ez[:, None] + 0.5 * (t[None] + 1.0)) / nz
     pi = np.pi
     sx, cx = np.sin(pi * X), np.cos(pi * X)
     sy, cy = np.sin(pi * Y), np.cos(pi * Y)
@@ -238,10 +291,14 @@ def warped_mesh(N: int, n_side: int = 32, elements: Optional[np.ndarray] = None,
     Ah[..., 2, 0] = warp * pi * cx * sy
     Ah[..., 2, 1] = warp * pi * sx * cy
     Ah[..., 2, 2] = 1.0
-    # dX_b / dxi_d = (h / 2) delta_bd ; x = length * xhat
-    A = Ah * (length * 0.5 * h)
-    xyz = length * np.stack([xh, yh, zh], axis=1)
-    return Mesh(N=N, Ne=Ne, geo=pack_geo(A), xyz=xyz, A=A, kind="warped")
+    # x_a = L_a xhat_a, dX_b / dxi_d = delta_bd / (2 n_b)
+    Lv = np.array([Lx, Ly, Lz])
+    nv = np.array([nx, ny, nz], dtype=np.float64)
+    A = Ah * Lv[:, None] * (0.5 / nv)[None, :]
+    xyz = np.stack([Lx * xh, Ly * yh, Lz * zh], axis=1)
+    geo = pack_geo(A) if metrics == "analytic" else curl_metric_geo(xyz, N)
+    return Mesh(N=N, Ne=Ne, geo=geo, xyz=xyz, A=A, kind="warped" if metrics == "analytic"
+                else "warped-curl")
 
 
 # --------------------------------------------------------------------------
@@ -344,13 +401,13 @@ def affine_workload(N: int = 4, n_side: int = 4, k: int = 1,
 
 
 def warped_workload(N: int = 7, n_side: int = 32, n_elements: Optional[int] = None,
-                    k: int = 2, with_adjoint: bool = False) -> Workload:
+                    k: int = 2, with_adjoint: bool = False, metrics: str = "analytic") -> Workload:
     """Warped-box workload: the first ``n_elements`` elements (default all
     ``n_side^3``) of the warped ``n_side^3`` box at order N (seed k)."""
     rng = np.random.default_rng(SEED_BASE + k)
     total = n_side ** 3
     n = total if n_elements is None else int(n_elements)
-    mesh = warped_mesh(N, n_side, np.arange(n))
+    mesh = warped_mesh(N, n_side, np.arange(n), metrics=metrics)
     return _finish(f"warped_N{N}_Ne{n}", N, mesh, rng, with_adjoint)
 
 
@@ -372,6 +429,45 @@ def adjoint_workload(N: int = 7, n_elements: int = 8192, k: int = 5) -> Workload
     rng = np.random.default_rng(SEED_BASE + k)
     mesh = warped_mesh(N, 32, np.arange(n_elements))
     return _finish(f"adjoint_N{N}_Ne{n_elements}", N, mesh, rng, True)
+
+
+def element_geo(geo: np.ndarray) -> np.ndarray:
+    """Per-element metric terms ``[Ne][10]`` of an affine mesh (whose per-node
+    terms ``geo[e][10][Nq^3]`` are constant in each element)."""
+    g = np.ascontiguousarray(geo[:, :, 0])
+    if np.max(np.ptp(geo, axis=2)) > 1e-12 * np.max(np.abs(geo)):
+        raise ValueError("metric terms vary inside an element: not an affine mesh")
+    return g
+
+
+def add_tracers(w: Workload, k: int = 100) -> Workload:
+    """The same workload with three passive tracers appended to the state:
+    ``Q_i = rho (0.2 i + 0.5 + 0.05 N(0,1))`` (seeded by ``k`` on a generator of
+    its own, so the other fields are unchanged)."""
+    rng = np.random.default_rng(SEED_BASE + k)
+    rho = w.q[:, :1]
+    Q = rho * (0.2 * np.arange(1, 4)[None, :, None] + 0.5
+               + 0.05 * rng.standard_normal((w.Ne, 3, w.q.shape[2])))
+    return dataclasses.replace(w, q=np.ascontiguousarray(np.concatenate([w.q, Q], axis=1)),
+                               name=w.name + "_tracers")
+
+
+# The paper's Table 2 keeps 3,538,944 nodes while Nq varies: Ne = 55296, 6912,
+# 2048, 864 at Nq = 4, 8, 12, 16 are the elements of a 2:2:1 box of
+# 192 x 192 x 96 nodes (nz = 96 / Nq elements vertically).
+TABLE2_NODES = 3538944
+
+
+def table2_workload(Nq: int, k: int = 7, tracers: bool = True) -> Workload:
+    """Warped 2 km x 2 km x 1 km box with (2 nz, 2 nz, nz) elements,
+    nz = 96 / Nq, i.e. the paper's constant 3,538,944-node workload."""
+    if 96 % Nq:
+        raise ValueError("Nq must divide 96 (Table 2 uses Nq = 4, 8, 12, 16)")
+    nz = 96 // Nq
+    rng = np.random.default_rng(SEED_BASE + k)
+    mesh = warped_mesh(Nq - 1, (2 * nz, 2 * nz, nz), length=(2 * LENGTH, 2 * LENGTH, LENGTH))
+    w = _finish(f"table2_Nq{Nq}_Ne{mesh.Ne}", Nq - 1, mesh, rng, False)
+    return add_tracers(w, 100 + k) if tracers else w
 
 
 def to_fp32(w: Workload) -> Workload:

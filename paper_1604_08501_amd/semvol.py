@@ -26,12 +26,13 @@ SEM_OK, SEM_ERR_INVALID_ARG, SEM_ERR_UNSUPPORTED, SEM_ERR_HIP, SEM_ERR_NO_MEMORY
 SEM_F64, SEM_F32 = 0, 1
 SEM_PLAN_AUTOTUNE, SEM_PLAN_USE_CACHE, SEM_RK3_SEPARATE_STAGES = 1, 2, 4
 SEM_LAYOUT_DEFAULT, SEM_LAYOUT_FULL, SEM_LAYOUT_ALIAS = 0, 1, 2
+SEM_DIR_R, SEM_DIR_S, SEM_DIR_T = 1, 2, 4
 LAYOUTS = {"default": SEM_LAYOUT_DEFAULT, "full": SEM_LAYOUT_FULL, "alias": SEM_LAYOUT_ALIAS}
 
 # every symbol include/sem.h declares
 EXPORTS = (
     "sem_last_error", "sem_version", "sem_tile_options", "sem_volume_rhs", "sem_volume_rhs_tiled",
-    "sem_volume_rhs_adjoint", "sem_axpby", "sem_batch_plan", "sem_batch_execute",
+    "sem_volume_rhs_ext", "sem_volume_rhs_affine", "sem_volume_rhs_adjoint", "sem_axpby", "sem_batch_plan", "sem_batch_execute",
     "sem_plan_describe", "sem_plan_destroy", "sem_rk3_graph_create", "sem_rk3_graph_launch",
     "sem_rk3_graph_describe", "sem_rk3_graph_destroy",
 )
@@ -78,6 +79,10 @@ def lib() -> ctypes.CDLL:
         "sem_volume_rhs": ([i32, i32, i32, vp, vp, vp, vp, vp, P(sem_phys), vp, i32, vp], i32),
         "sem_volume_rhs_tiled": ([i32, i32, i32, vp, vp, vp, vp, vp, P(sem_phys), vp, i32,
                                   P(sem_tile), vp], i32),
+        "sem_volume_rhs_ext": ([i32, i32, i32, i32, u32, vp, vp, vp, vp, vp, P(sem_phys), vp, i32,
+                                vp], i32),
+        "sem_volume_rhs_affine": ([i32, i32, i32, vp, vp, vp, vp, vp, P(sem_phys), vp, i32, vp],
+                                  i32),
         "sem_volume_rhs_adjoint": ([i32, i32, i32, vp, vp, vp, P(sem_phys), vp, vp, i32, vp], i32),
         "sem_axpby": ([i64, i32, d, vp, d, vp, d, vp, vp, vp], i32),
         "sem_batch_plan": ([P(sem_block), i32, i32, P(sem_phys), u32, vp, P(vp)], i32),
@@ -187,6 +192,48 @@ def volume_rhs(q, geo, D, rho_ref=None, theta_ref=None, phys=None, out=None, acc
     return out
 
 
+def volume_rhs_ext(q, geo, D, rho_ref=None, theta_ref=None, phys=None, dirs=7, out=None,
+                   accumulate=False, stream=None) -> torch.Tensor:
+    """Volume term with 5 or 8 fields (``q`` ``[Ne, nf, Nq^3]``, fields 5-7 the
+    passive tracers) over the reference directions ``dirs`` (3 = r+s, the
+    paper's benchmark kernel; 7 = r+s+t); Nq up to 16."""
+    if q.dim() != 3 or q.shape[1] not in (5, 8):
+        raise ValueError(f"q must be [Ne, 5 or 8, Nq^3], got {tuple(q.shape)}")
+    Ne, nf = q.shape[0], q.shape[1]
+    Nq = D.shape[0]
+    M = Nq ** 3
+    if D.dim() != 2 or D.shape[1] != Nq or q.shape[2] != M:
+        raise ValueError(f"D [{tuple(D.shape)}] does not match q [{tuple(q.shape)}]")
+    dt = q.dtype
+    if out is None:
+        out = torch.empty_like(q)
+    ph = _phys(phys)
+    _check(lib().sem_volume_rhs_ext(
+        Ne, Nq, _code(dt), nf, int(dirs), _dev(D, "D", dt), _dev(geo, "geo", dt, (Ne, 10, M)),
+        _dev(q, "q", dt), _dev(rho_ref, "rho_ref", dt, (Ne, M)),
+        _dev(theta_ref, "theta_ref", torch.float64, (Ne, M)), ctypes.byref(ph),
+        _dev(out, "out", dt, q.shape), int(bool(accumulate)), _stream(stream)))
+    return out
+
+
+def volume_rhs_affine(q, geo_elem, D, rho_ref=None, theta_ref=None, phys=None, out=None,
+                      accumulate=False, stream=None) -> torch.Tensor:
+    """Volume term for affine elements: ``geo_elem`` ``[Ne, 10]`` holds the
+    metric terms and 1/J once per element."""
+    Ne, Nq = _shape(q, D)
+    M = Nq ** 3
+    dt = q.dtype
+    if out is None:
+        out = torch.empty_like(q)
+    ph = _phys(phys)
+    _check(lib().sem_volume_rhs_affine(
+        Ne, Nq, _code(dt), _dev(D, "D", dt), _dev(geo_elem, "geo_elem", dt, (Ne, 10)),
+        _dev(q, "q", dt), _dev(rho_ref, "rho_ref", dt, (Ne, M)),
+        _dev(theta_ref, "theta_ref", torch.float64, (Ne, M)), ctypes.byref(ph),
+        _dev(out, "out", dt, q.shape), int(bool(accumulate)), _stream(stream)))
+    return out
+
+
 def volume_rhs_adjoint(q, geo, D, lam, phys=None, out=None, accumulate=False,
                        stream=None) -> torch.Tensor:
     """Vector-Jacobian product ``(dv/dq)^T lam`` (the reference state drops out)."""
@@ -254,7 +301,7 @@ def _blocks(blocks: Sequence[dict], dtype: torch.dtype):
 class BatchPlan:
     """Mixed-order batch: ``blocks`` is a list of dicts with tensors ``q``,
     ``geo``, ``D``, ``rhs`` and optional ``rho_ref``/``theta_ref``; every
-    block may have its own order.  ``execute()`` is one persistent launch."""
+    block may have its own order.  ``execute()`` is one kernel launch."""
 
     def __init__(self, blocks: Sequence[dict], phys=None, autotune: bool = False,
                  use_cache: bool = False, stream=None):

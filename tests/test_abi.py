@@ -157,3 +157,35 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(semvol, "LIB_PATH", "/nonexistent/libsem.so")
     with pytest.raises(ImportError):
         semvol.lib()
+
+
+def test_ext_validation(L, sv):
+    ph = sv.sem_phys(1.0, 1.4, 1.0, 0.0)
+
+    def ext(Ne=4, Nq=8, dt=1, nf=8, dirs=3, q=3 * A, rhs=4 * A):
+        return L.sem_volume_rhs_ext(Ne, Nq, dt, nf, dirs, A, 2 * A, q, None, None,
+                                    ctypes.byref(ph), rhs, 0, None)
+    assert ext(Ne=0) == sv.SEM_ERR_INVALID_ARG
+    assert ext(nf=6) == sv.SEM_ERR_UNSUPPORTED
+    assert ext(dirs=5) == sv.SEM_ERR_UNSUPPORTED
+    assert ext(dirs=1) == sv.SEM_ERR_UNSUPPORTED
+    assert ext(Nq=11) == sv.SEM_ERR_UNSUPPORTED
+    assert ext(Nq=16, dt=0) == sv.SEM_ERR_UNSUPPORTED      # FP64 at Nq = 16 exceeds the LDS
+    assert b"Nq = 16" in L.sem_last_error()
+    assert ext(q=3 * A + 2) == sv.SEM_ERR_INVALID_ARG      # misaligned FP32 array
+    assert ext(rhs=3 * A) == sv.SEM_ERR_INVALID_ARG        # rhs aliases q
+    assert ext(dt=9) == sv.SEM_ERR_INVALID_ARG
+
+
+def test_affine_validation(L, sv):
+    ph = sv.sem_phys(1e5, 1.4, 287.0, 9.81)
+
+    def aff(Ne=4, Nq=8, dt=0, geo=2 * A, rhs=4 * A):
+        return L.sem_volume_rhs_affine(Ne, Nq, dt, A, geo, 3 * A, None, None, ctypes.byref(ph),
+                                       rhs, 0, None)
+    assert aff(Ne=0) == sv.SEM_ERR_INVALID_ARG
+    assert aff(Nq=11) == sv.SEM_ERR_UNSUPPORTED
+    assert aff(Nq=16) == sv.SEM_ERR_UNSUPPORTED
+    assert aff(geo=None) == sv.SEM_ERR_INVALID_ARG
+    assert aff(geo=2 * A + 4) == sv.SEM_ERR_INVALID_ARG
+    assert aff(rhs=2 * A) == sv.SEM_ERR_INVALID_ARG

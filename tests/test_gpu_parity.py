@@ -310,3 +310,98 @@ def test_rk3_graph(sv, oracle_mod, dtype, separate):
             assert e.max() <= tol, (replay, w.N, e)
             off += sz
     g.close()
+
+
+# ---------------------------------------------------------------------------
+# Extended volume term: passive tracers, r+s or r+s+t, Nq up to 16
+# ---------------------------------------------------------------------------
+EXT_EPB = {2: 64, 3: 16, 4: 8, 5: 4, 6: 2}
+
+
+@pytest.mark.parametrize("Nq", [2, 3, 4, 5, 6, 8, 9, 10, 12, 16])
+@pytest.mark.parametrize("nf,dirs", [(5, 3), (8, 3), (8, 7), (5, 7)])
+def test_ext_vs_oracle(sv, oracle_mod, Nq, nf, dirs):
+    Ne = 2 * EXT_EPB.get(Nq, 1) + 1                  # several tiles and a ragged tail
+    w = I.warped_workload(N=Nq - 1, n_elements=Ne, k=100 + Nq)
+    if nf == 8:
+        w = I.add_tracers(w)
+    phys = w.phys.as_tuple()
+    ref = oracle_mod.volume_rhs_ext(w.D, w.geo, w.q, w.rho_ref, w.theta_ref, phys, dirs=dirs)
+    # FP64
+    args = (dev(w.q), dev(w.geo), dev(w.D), dev(w.rho_ref), dev(w.theta_ref), phys)
+    if Nq == 16:
+        with pytest.raises(sv.SemError):          # does not fit the LDS in FP64
+            sv.volume_rhs_ext(*args, dirs=dirs)
+    else:
+        e = err(host(sv.volume_rhs_ext(*args, dirs=dirs)), ref)
+        assert e.max() <= TOL64, (Nq, nf, dirs, e)
+        base = np.random.default_rng(Nq).standard_normal(w.q.shape)
+        out = dev(base.copy())
+        sv.volume_rhs_ext(*args, dirs=dirs, out=out, accumulate=True)
+        assert err(host(out), base + ref).max() <= TOL64
+    # FP32 on the rounded inputs
+    w32 = I.to_fp32(w)
+    u = I.upcast(w32)
+    ref32 = oracle_mod.volume_rhs_ext(u.D, u.geo, u.q, u.rho_ref, u.theta_ref, phys, dirs=dirs)
+    out32 = sv.volume_rhs_ext(dev(w32.q), dev(w32.geo), dev(w32.D), dev(w32.rho_ref),
+                              dev(w32.theta_ref), phys, dirs=dirs)
+    e32 = err(host(out32), ref32)
+    assert e32.max() <= TOL32, (Nq, nf, dirs, e32)
+
+
+def test_ext_paper_constants(sv, oracle_mod):
+    """The paper's benchmark configuration: 8 fields, r and s only, p0 = 1,
+    gamma = 1.4, R = 1, no gravity, no reference state, rhsq accumulated."""
+    phys = (1.0, 1.4, 1.0, 0.0)
+    w = I.add_tracers(I.warped_workload(N=7, n_elements=40, k=120))
+    w32 = I.to_fp32(w)
+    u = I.upcast(w32)
+    base = np.random.default_rng(5).standard_normal(w.q.shape).astype(np.float32)
+    ref = oracle_mod.volume_rhs_ext(u.D, u.geo, u.q, None, None, phys, dirs=3,
+                                    out=base.astype(np.float64), accumulate=True)
+    out = dev(base.copy())
+    sv.volume_rhs_ext(dev(w32.q), dev(w32.geo), dev(w32.D), None, None, phys, dirs=3, out=out,
+                      accumulate=True)
+    assert err(host(out), ref).max() <= TOL32
+
+
+# ---------------------------------------------------------------------------
+# Per-element metric terms (affine elements)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("Nq", [2, 3, 4, 5, 8, 10, 12, 16])
+def test_affine_per_element_geometry(sv, oracle_mod, Nq):
+    n_side = 3 if Nq <= 8 else 2
+    w = I.affine_workload(N=Nq - 1, n_side=n_side, k=130 + Nq, with_adjoint=False)
+    phys = w.phys.as_tuple()
+    ref = oracle_mod.volume_rhs(w.D, w.geo, w.q, w.rho_ref, w.theta_ref, phys)
+    ge = I.element_geo(w.geo)
+    if Nq == 16:
+        with pytest.raises(sv.SemError):
+            sv.volume_rhs_affine(dev(w.q), dev(ge), dev(w.D), dev(w.rho_ref), dev(w.theta_ref), phys)
+    else:
+        out = sv.volume_rhs_affine(dev(w.q), dev(ge), dev(w.D), dev(w.rho_ref), dev(w.theta_ref),
+                                   phys)
+        assert err(host(out), ref).max() <= TOL64, Nq
+    w32 = I.to_fp32(w)
+    u = I.upcast(w32)
+    ref32 = oracle_mod.volume_rhs(u.D, u.geo, u.q, u.rho_ref, u.theta_ref, phys)
+    out32 = sv.volume_rhs_affine(dev(w32.q), dev(I.element_geo(w32.geo)), dev(w32.D),
+                                 dev(w32.rho_ref), dev(w32.theta_ref), phys)
+    assert err(host(out32), ref32).max() <= TOL32, Nq
+
+
+@pytest.mark.parametrize("N", [2, 4, 7])
+def test_curl_metrics_free_stream_on_gpu(sv, oracle_mod, N):
+    """With curl-form metric terms a uniform state keeps zero flux divergence
+    on curved elements; the GPU result equals the oracle's."""
+    w = I.warped_workload(N=N, n_elements=40, k=140 + N, metrics="curl")
+    q = np.zeros_like(w.q)
+    for b, val in enumerate([1.1, 3.0, -4.0, 2.5, 1.1 * 301.0]):
+        q[:, b] = val
+    phys = (I.P0, I.GAMMA, I.R_GAS, 0.0)
+    out = host(sv.volume_rhs(dev(q), dev(w.geo), dev(w.D), phys=phys))
+    assert np.abs(out).max() < 1e-8
+    wr = oracle_mod.volume_rhs(w.D, w.geo, w.q, w.rho_ref, w.theta_ref, w.phys.as_tuple())
+    got = host(sv.volume_rhs(dev(w.q), dev(w.geo), dev(w.D), dev(w.rho_ref), dev(w.theta_ref),
+                             w.phys.as_tuple()))
+    assert err(got, wr).max() <= TOL64

@@ -134,3 +134,41 @@ def test_workload_draws_are_reproducible():
     assert 0.9 < rho.min() and rho.max() < 1.1
     theta = a.q[:, 4] / rho
     assert 290 < theta.min() and theta.max() < 310
+
+
+# ---------------------------------------------------------------------------
+# Curl-form metric terms
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("N", [2, 4, 7])
+def test_curl_metrics_satisfy_discrete_identities(N):
+    """sum_d D_d g_ad = 0 at every node, to round-off."""
+    mesh = I.warped_mesh(N, 32, np.array([0, 77, 5000, 32767]), metrics="curl")
+    D = I.diff_matrix(N)
+    g = mesh.geo
+    scale = np.abs(D).sum(1).max() * np.abs(g[:, :9]).max()
+    for a in range(3):
+        div = sum(I._nodal_derivative(D, g[:, 3 * d + a], d) for d in range(3))
+        assert np.abs(div).max() < 1e-13 * scale, (a, np.abs(div).max() / scale)
+    # the analytic metric terms miss them on curved elements by a truncation
+    # error that decays with N (visible at low order)
+    if N == 2:
+        ga = I.warped_mesh(N, 32, np.array([0, 77, 5000, 32767])).geo
+        div = sum(I._nodal_derivative(D, ga[:, 3 * d + 0], d) for d in range(3))
+        assert np.abs(div).max() > 1e-8 * scale
+
+
+def test_curl_metrics_exact_on_affine_elements():
+    rng = np.random.default_rng(4)
+    mesh = I.affine_mesh(3, rng, n_side=2)
+    g = I.curl_metric_geo(mesh.xyz, 3)
+    np.testing.assert_allclose(g, mesh.geo, rtol=1e-12, atol=1e-13 * np.abs(mesh.geo).max())
+
+
+def test_curl_metrics_converge_to_analytic():
+    errs = []
+    for N in (2, 3, 4, 5, 6):
+        els = np.array([0, 77, 5000, 32767])
+        ga = I.warped_mesh(N, 32, els).geo
+        gc = I.warped_mesh(N, 32, els, metrics="curl").geo
+        errs.append(np.abs(gc[:, :9] - ga[:, :9]).max() / np.abs(ga[:, :9]).max())
+    assert all(b < 0.2 * a for a, b in zip(errs, errs[1:])), errs
