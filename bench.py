@@ -9,13 +9,16 @@ term (one kernel launch over all elements) with inputs resident in HBM.
 ``value`` is the FP64 rate; the FP32 form of the same workload is reported
 beside it, with its error against the FP64 oracle and the FP32/FP64 speedup.
 
-Beside it the line carries the mixed-order persistent batch (N = 3, 5, 7, 9,
+Beside it the line carries the mixed-order batch (N = 3, 5, 7, 9,
 5000 elements each; autotuned), one SSP-RK3 step replayed from a HIP graph
 (stage updates fused into the batch launch, and as separate RHS + axpby
 launches), and the adjoint (N=7, 8192 elements), each in FP64 and FP32, and
 the paper-comparable configuration on the Table 2 shapes (FP32, 8 fields,
 r+s and r+s+t, Nq = 4, 8, 12, 16 at 3,538,944 nodes) with the paper's own
-timings on its hardware quoted beside it as context.
+timings on its hardware quoted beside it as context, and the per-element
+metric form on an affine N=7 mesh of 32768 elements against the per-node
+form of the same mesh, and the optimisation ladder of the paper's
+benchmark kernel (levels 1-6) at Nq = 8 on the Table 2 shape.
 The warm-up (30 launches by default) lets the clock settle before the timed
 launches, so the rate is the sustained one.
 
@@ -90,7 +93,7 @@ def time_launches(fn, steps: int, warmup: int, stream):
 
 def bench_batch_and_rk3(sv, I, steps: int, warmup: int, stream):
     """Mixed-order batch (N = 3, 5, 7, 9; 5000 warped elements each) as one
-    persistent launch, autotuned, and one SSP-RK3 step (dt = 1e-3) replayed
+    launch, autotuned, and one SSP-RK3 step (dt = 1e-3) replayed
     from a HIP graph; FP64 and FP32.  Returns timings and algorithmic rates."""
     import torch
     ws = I.mixed_order_workloads()
@@ -202,6 +205,79 @@ def bench_paper_table2(sv, I, steps: int, warmup: int, stream):
     return out
 
 
+# The paper's Table 1 (its r+s, 8-field FP32 kernel at Nq = 8, Ne = 6910):
+# wall time of its naive level 1 and its final level 8, in ms, for context.
+PAPER_TABLE1_MS = {"R9 Fury X": (25.01630, 1.36121), "GTX Titan X": (7.17732, 2.06197),
+                   "Tesla K40c": (14.29650, 3.28481)}
+
+
+def bench_ladder(sv, I, steps: int, warmup: int, stream):
+    """Optimisation ladder of the paper's benchmark kernel on the Table 2
+    shape at Nq = 8 (6912 warped elements, 8 fields, FP32, r+s, rhs += v,
+    p0 = 1, gamma = 1.4, R = 1): time per level and speedup over level 1."""
+    import torch
+    phys = (1.0, 1.4, 1.0, 0.0)
+    w = I.to_fp32(I.table2_workload(8))
+    nodes = w.Ne * w.Nq ** 3
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    q, geo, D = t(w.q), t(w.geo), t(w.D)
+    rhs = torch.zeros_like(q)
+    # the bytes the final kernel must move: q 8, metric terms 6 + 1/J, rhs 8
+    # read and 8 written, 4 bytes each
+    byt = (8 + 7 + 16) * 4 * nodes
+    out = {"workload": f"Nq=8, {w.Ne} warped elements, 8 fields, FP32, r+s, rhsq += v",
+           "paper_table1_ms_level1_level8": PAPER_TABLE1_MS, "levels": {}}
+    base = None
+    for level in range(1, sv.LADDER_LEVELS + 1):
+        n_steps = steps if level >= 3 else max(3, steps // 10)
+        ms, _ = time_launches(lambda: sv.volume_rhs_ladder(level, q, geo, D, phys, out=rhs),
+                              n_steps, min(warmup, 3) if level < 3 else warmup, stream)
+        base = base or ms
+        out["levels"][str(level)] = {"ms": ms, "speedup_vs_level1": base / ms,
+                                     "GBs_final_kernel_bytes": byt / (ms * 1e-3) / 1e9}
+    del q, geo, D, rhs
+    torch.cuda.empty_cache()
+    return out
+
+
+def bench_affine(sv, I, steps: int, warmup: int, stream):
+    """Per-element metric terms on an affine mesh: N=7, 32^3 = 32768 affine
+    elements, FP64 and FP32, against the per-node form of the same mesh, and the optimisation ladder of the paper's
+benchmark kernel (levels 1-6) at Nq = 8 on the Table 2 shape.
+    The per-element form reads 10 words per element instead of 10 per node."""
+    import torch
+    w = I.affine_workload(N=7, n_side=32, k=1, with_adjoint=False)
+    nodes = w.Ne * w.Nq ** 3
+    out = {"workload": "N=7, 32768 affine elements (16.8 M nodes), 5 fields, r+s+t",
+           "nodes": nodes}
+    ge = I.element_geo(w.geo)
+    for tag, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        src = w if dt == torch.float64 else I.to_fp32(w)
+        cast = (lambda a: a) if dt == torch.float64 else (lambda a: np.asarray(a, np.float32))
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        q, geo, D, rr, tr = t(src.q), t(src.geo), t(src.D), t(src.rho_ref), t(src.theta_ref)
+        g_el = t(cast(ge))
+        o1, o2 = torch.empty_like(q), torch.empty_like(q)
+        ph = w.phys.as_tuple()
+        ms_node, _ = time_launches(lambda: sv.volume_rhs(q, geo, D, rr, tr, ph, out=o1),
+                                   steps, warmup, stream)
+        ms_elem, _ = time_launches(lambda: sv.volume_rhs_affine(q, g_el, D, rr, tr, ph, out=o2),
+                                   steps, warmup, stream)
+        torch.cuda.synchronize()
+        diff = float(I.rel_err_per_field(o2.cpu().numpy(), o1.cpu().numpy()).max())
+        esz = 8 if tag == "f64" else 4
+        # per node: q 5 + rho_ref read, rhs 5 written (dtype) + theta_ref (FP64);
+        # per element: 10 metric words
+        byt = (11 * esz + 8) * nodes + 10 * esz * w.Ne
+        out[tag] = {"per_element_ms": ms_elem, "per_node_ms": ms_node,
+                    "el_s": w.Ne / (ms_elem * 1e-3), "GBs": byt / (ms_elem * 1e-3) / 1e9,
+                    "bytes": byt, "speedup_vs_per_node": ms_node / ms_elem,
+                    "max_rel_diff_vs_per_node": diff}
+        del q, geo, D, rr, tr, g_el, o1, o2
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, budget_s: float):
     import oracle
     phys = w.phys.as_tuple()
@@ -228,7 +304,7 @@ def main(argv=None):
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-extra", action="store_true",
-                    help="skip the mixed-order batch / RK3 graph and adjoint measurements")
+                    help="skip the mixed-order batch / RK3 graph, adjoint, Table 2 and affine measurements")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only time a plain device-to-device copy of GIB GiB (the reference "
                          "for measured HBM bandwidth and for the PMC byte-counter scale)")
@@ -332,6 +408,8 @@ def main(argv=None):
         line["batch_mixed_order"] = bench_batch_and_rk3(sv, I, a.steps, a.warmup, stream)
         line["adjoint"] = bench_adjoint(sv, I, a.steps, a.warmup, stream)
         line["paper_table2"] = bench_paper_table2(sv, I, a.steps, a.warmup, stream)
+        line["affine_per_element"] = bench_affine(sv, I, a.steps, a.warmup, stream)
+        line["opt_ladder"] = bench_ladder(sv, I, a.steps, a.warmup, stream)
     if not a.no_cpu:
         line["cpu_baseline"] = cpu_baseline(w, a.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -158,6 +158,35 @@ sem_status sem_volume_rhs_ext(int32_t Ne, int32_t Nq, sem_dtype dtype, int32_t n
                               void* stream);
 
 /*
+ * Optimisation ladder (the analogue of the per-level timings of Sec. 4,
+ * Table 1) of the paper's benchmark kernel: the fused r+s volume term of
+ * Eq. (volterm) with the 8-field prognostic vector of Sec. 2, FP32, no
+ * reference state and no source, accumulated:
+ *   rhs += -(1/J) sum_{d in r,s} D_d (sum_a g_ad f_a)
+ * Every level computes the same values (up to FP32 rounding order):
+ *   1  naive: per output node and per n, state, metric terms, pressure and
+ *      flux at the line node from global memory, D from global memory, rhs
+ *      read-modify-written in global memory for every term;
+ *   2  + D in LDS;
+ *   3  + fluxes evaluated once per node into LDS, a k-slice at a time;
+ *   4  + rhs accumulated in registers, one global update per output;
+ *   5  + 1/J applied once per output;
+ *   6  the production kernel (sem_volume_rhs_ext with nfields = 8, r+s).
+ * Levels 1-5 use one workgroup per element and one lane per (i, j) node.
+ *   Nq      2..10, 12, 16
+ *   D, geo, q, rhs   FP32 device arrays as for sem_volume_rhs_ext (nfields 8);
+ *                    geo slots 6-8 (the t direction) are not read
+ *   phys    p0, gamma, R; grav must be 0
+ * Errors: level outside 1..SEM_LADDER_LEVELS, Ne < 1, NULL or misaligned
+ * pointers, rhs aliasing an input -> SEM_ERR_INVALID_ARG; unsupported Nq or
+ * grav != 0 -> SEM_ERR_UNSUPPORTED.  Allocates nothing.
+ */
+#define SEM_LADDER_LEVELS 6
+sem_status sem_volume_rhs_ladder(int32_t level, int32_t Ne, int32_t Nq, const void* D,
+                                 const void* geo, const void* q, const sem_phys* phys,
+                                 void* rhs, void* stream);
+
+/*
  * Volume term of sem_volume_rhs for affine elements, whose metric terms g and
  * 1/J are constant in each element (Sec. 2 names them geometric factors of the
  * reference-to-physical map; for x = A xi + b they do not vary inside the

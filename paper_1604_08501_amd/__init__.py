@@ -8,5 +8,5 @@ states; ``build`` compiles the library.
 """
 from .semvol import (  # noqa: F401
     SemError, VolumeRHS, BatchPlan, RK3Graph, axpby, lib, tile_options, version, volume_rhs,
-    volume_rhs_adjoint, volume_rhs_ext, volume_rhs_affine,
+    volume_rhs_adjoint, volume_rhs_ext, volume_rhs_affine, volume_rhs_ladder, LADDER_LEVELS,
 )

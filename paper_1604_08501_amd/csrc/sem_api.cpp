@@ -265,6 +265,32 @@ extern "C" sem_status sem_volume_rhs_ext(int32_t Ne, int32_t Nq, sem_dtype dtype
     return SEM_OK;
 }
 
+extern "C" sem_status sem_volume_rhs_ladder(int32_t level, int32_t Ne, int32_t Nq, const void* D,
+                                            const void* geo, const void* q, const sem_phys* phys,
+                                            void* rhs, void* stream)
+{
+    if (level < 1 || level > SEM_LADDER_LEVELS)
+        return fail(SEM_ERR_INVALID_ARG, "level = %d (1..%d)", level, SEM_LADDER_LEVELS);
+    if (Ne < 1)
+        return fail(SEM_ERR_INVALID_ARG, "Ne = %d: at least one element is required", Ne);
+    if (!semh::ladder_supported(Nq) || !semh::ext_supported<float>(Nq, 8, 3))
+        return fail(SEM_ERR_UNSUPPORTED, "Nq = %d is not compiled (Nq 2..10, 12, 16)", Nq);
+    SEM_TRY(check_volume_ptrs(SEM_F32, D, geo, q, nullptr, nullptr, phys, rhs));
+    if (phys->grav != 0.0)
+        return fail(SEM_ERR_UNSUPPORTED,
+                    "grav = %g: the benchmark kernel has no source term (grav must be 0)", phys->grav);
+    if (level == SEM_LADDER_LEVELS)
+        return sem_volume_rhs_ext(Ne, Nq, SEM_F32, 8, SEM_DIR_R | SEM_DIR_S, D, geo, q, nullptr,
+                                  nullptr, phys, rhs, 1, stream);
+    const hipError_t err = semh::launch_ladder(
+        level, Nq, Ne, static_cast<const float*>(D), static_cast<const float*>(geo),
+        static_cast<const float*>(q), static_cast<float*>(rhs), to_phys(phys),
+        static_cast<hipStream_t>(stream));
+    if (err != hipSuccess)
+        return hip_fail(err, "ladder kernel launch");
+    return SEM_OK;
+}
+
 extern "C" sem_status sem_volume_rhs_affine(int32_t Ne, int32_t Nq, sem_dtype dtype, const void* D,
                                             const void* geo_elem, const void* q,
                                             const void* rho_ref, const double* theta_ref,

@@ -69,6 +69,12 @@ template <typename T>
 hipError_t launch_volume_affine(int nq, const semk::BlockPtrs<T>& B, const semk::Phys& ph,
                                 int accumulate, hipStream_t s);
 
+// Optimisation ladder of the fused r+s, 8-field FP32 kernel (ladder.hip):
+// levels 1..5, Nq 2..10, 12, 16.
+bool ladder_supported(int nq);
+hipError_t launch_ladder(int level, int nq, int64_t Ne, const float* D, const float* geo,
+                         const float* q, float* rhs, const semk::Phys& ph, hipStream_t s);
+
 // Mixed-order batch kernel (defined per dtype in batch_*.hip): one tile per
 // workgroup.
 struct Tile {

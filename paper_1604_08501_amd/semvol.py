@@ -32,7 +32,8 @@ LAYOUTS = {"default": SEM_LAYOUT_DEFAULT, "full": SEM_LAYOUT_FULL, "alias": SEM_
 # every symbol include/sem.h declares
 EXPORTS = (
     "sem_last_error", "sem_version", "sem_tile_options", "sem_volume_rhs", "sem_volume_rhs_tiled",
-    "sem_volume_rhs_ext", "sem_volume_rhs_affine", "sem_volume_rhs_adjoint", "sem_axpby", "sem_batch_plan", "sem_batch_execute",
+    "sem_volume_rhs_ext", "sem_volume_rhs_ladder", "sem_volume_rhs_affine", "sem_volume_rhs_adjoint",
+    "sem_axpby", "sem_batch_plan", "sem_batch_execute",
     "sem_plan_describe", "sem_plan_destroy", "sem_rk3_graph_create", "sem_rk3_graph_launch",
     "sem_rk3_graph_describe", "sem_rk3_graph_destroy",
 )
@@ -81,6 +82,7 @@ def lib() -> ctypes.CDLL:
                                   P(sem_tile), vp], i32),
         "sem_volume_rhs_ext": ([i32, i32, i32, i32, u32, vp, vp, vp, vp, vp, P(sem_phys), vp, i32,
                                 vp], i32),
+        "sem_volume_rhs_ladder": ([i32, i32, i32, vp, vp, vp, P(sem_phys), vp, vp], i32),
         "sem_volume_rhs_affine": ([i32, i32, i32, vp, vp, vp, vp, vp, P(sem_phys), vp, i32, vp],
                                   i32),
         "sem_volume_rhs_adjoint": ([i32, i32, i32, vp, vp, vp, P(sem_phys), vp, vp, i32, vp], i32),
@@ -213,6 +215,30 @@ def volume_rhs_ext(q, geo, D, rho_ref=None, theta_ref=None, phys=None, dirs=7, o
         _dev(q, "q", dt), _dev(rho_ref, "rho_ref", dt, (Ne, M)),
         _dev(theta_ref, "theta_ref", torch.float64, (Ne, M)), ctypes.byref(ph),
         _dev(out, "out", dt, q.shape), int(bool(accumulate)), _stream(stream)))
+    return out
+
+
+LADDER_LEVELS = 6
+
+
+def volume_rhs_ladder(level, q, geo, D, phys=None, out=None, stream=None) -> torch.Tensor:
+    """The paper's benchmark kernel (FP32, 8 fields, r and s, no reference
+    state, no source; ``out += v``) at optimisation level ``level`` (1 naive ..
+    5, 6 = production kernel).  ``out`` is accumulated into (zeros if None)."""
+    if q.dim() != 3 or q.shape[1] != 8:
+        raise ValueError(f"q must be [Ne, 8, Nq^3], got {tuple(q.shape)}")
+    Ne = q.shape[0]
+    Nq = D.shape[0]
+    M = Nq ** 3
+    if D.dim() != 2 or D.shape[1] != Nq or q.shape[2] != M:
+        raise ValueError(f"D [{tuple(D.shape)}] does not match q [{tuple(q.shape)}]")
+    dt = torch.float32
+    if out is None:
+        out = torch.zeros_like(q)
+    ph = _phys(phys)
+    _check(lib().sem_volume_rhs_ladder(
+        int(level), Ne, Nq, _dev(D, "D", dt), _dev(geo, "geo", dt, (Ne, 10, M)), _dev(q, "q", dt),
+        ctypes.byref(ph), _dev(out, "out", dt, q.shape), _stream(stream)))
     return out
 
 

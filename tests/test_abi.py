@@ -189,3 +189,22 @@ def test_affine_validation(L, sv):
     assert aff(geo=None) == sv.SEM_ERR_INVALID_ARG
     assert aff(geo=2 * A + 4) == sv.SEM_ERR_INVALID_ARG
     assert aff(rhs=2 * A) == sv.SEM_ERR_INVALID_ARG
+
+
+def test_ladder_validation(L, sv):
+    ph = sv.sem_phys(1.0, 1.4, 1.0, 0.0)
+    grav = sv.sem_phys(1.0, 1.4, 1.0, 9.81)
+
+    def lad(level=1, Ne=4, Nq=8, q=3 * A, rhs=4 * A, phys=ph):
+        return L.sem_volume_rhs_ladder(level, Ne, Nq, A, 2 * A, q, ctypes.byref(phys), rhs, None)
+    assert lad(level=0) == sv.SEM_ERR_INVALID_ARG
+    assert lad(level=7) == sv.SEM_ERR_INVALID_ARG
+    assert b"level" in L.sem_last_error()
+    assert lad(Ne=0) == sv.SEM_ERR_INVALID_ARG
+    assert lad(Nq=11) == sv.SEM_ERR_UNSUPPORTED
+    assert lad(Nq=1) == sv.SEM_ERR_UNSUPPORTED
+    assert lad(phys=grav) == sv.SEM_ERR_UNSUPPORTED
+    assert lad(q=3 * A + 2) == sv.SEM_ERR_INVALID_ARG
+    assert lad(rhs=3 * A) == sv.SEM_ERR_INVALID_ARG
+    assert L.sem_volume_rhs_ladder(1, 4, 8, A, 2 * A, 3 * A, None, 4 * A, None) == \
+        sv.SEM_ERR_INVALID_ARG

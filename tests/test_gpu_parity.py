@@ -405,3 +405,36 @@ def test_curl_metrics_free_stream_on_gpu(sv, oracle_mod, N):
     got = host(sv.volume_rhs(dev(w.q), dev(w.geo), dev(w.D), dev(w.rho_ref), dev(w.theta_ref),
                              w.phys.as_tuple()))
     assert err(got, wr).max() <= TOL64
+
+
+# ---------------------------------------------------------------------------
+# Optimisation ladder of the paper's benchmark kernel (FP32, 8 fields, r+s)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("Nq", [2, 3, 4, 8, 12, 16])
+def test_ladder_levels_vs_oracle(sv, oracle_mod, Nq):
+    """Every level of the ladder computes the paper's kernel: rhs += v with 8
+    fields, the r and s terms, p0 = 1, gamma = 1.4, R = 1, no source."""
+    phys = (1.0, 1.4, 1.0, 0.0)
+    Ne = 5
+    w = I.add_tracers(I.warped_workload(N=Nq - 1, n_elements=Ne, k=150 + Nq))
+    w32 = I.to_fp32(w)
+    u = I.upcast(w32)
+    base = np.random.default_rng(Nq).standard_normal(w.q.shape).astype(np.float32)
+    ref = oracle_mod.volume_rhs_ext(u.D, u.geo, u.q, None, None, phys, dirs=3,
+                                    out=base.astype(np.float64), accumulate=True)
+    q, geo, D = dev(w32.q), dev(w32.geo), dev(w32.D)
+    for level in range(1, sv.LADDER_LEVELS + 1):
+        out = dev(base.copy())
+        sv.volume_rhs_ladder(level, q, geo, D, phys, out=out)
+        e = err(host(out), ref)
+        assert e.max() <= TOL32, (Nq, level, e)
+
+
+def test_ladder_rejects_source_and_bad_level(sv):
+    w32 = I.to_fp32(I.add_tracers(I.warped_workload(N=3, n_elements=2, k=160)))
+    q, geo, D = dev(w32.q), dev(w32.geo), dev(w32.D)
+    with pytest.raises(sv.SemError):
+        sv.volume_rhs_ladder(1, q, geo, D, (1.0, 1.4, 1.0, 9.81))
+    for level in (0, sv.LADDER_LEVELS + 1):
+        with pytest.raises(sv.SemError):
+            sv.volume_rhs_ladder(level, q, geo, D, (1.0, 1.4, 1.0, 0.0))
