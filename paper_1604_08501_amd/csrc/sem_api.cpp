@@ -16,7 +16,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/sem.h"
+#include "sem.h"
 #include "sem_internal.hpp"
 
 namespace {
