@@ -438,3 +438,113 @@ def test_ladder_rejects_source_and_bad_level(sv):
     for level in (0, sv.LADDER_LEVELS + 1):
         with pytest.raises(sv.SemError):
             sv.volume_rhs_ladder(level, q, geo, D, (1.0, 1.4, 1.0, 0.0))
+
+
+# ---------------------------------------------------------------------------
+# Full-size cases in the launch configurations the benchmark times
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c4():
+    return I.mixed_order_workloads()            # 5000 elements at each of N = 3, 5, 7, 9
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_full_mixed_order_batch_autotuned(sv, oracle_mod, c4, dtype):
+    blocks = _batch(c4, dtype)
+    plan = sv.BatchPlan(blocks, c4[0].phys.as_tuple(), autotune=True)
+    plan.execute()
+    for w, b in zip(c4, blocks):
+        src = w if dtype == torch.float64 else I.upcast(I.to_fp32(w))
+        e = err(host(b["rhs"]), oracle_fwd(oracle_mod, src))
+        assert e.max() <= (TOL64 if dtype == torch.float64 else TOL32), (w.N, e)
+    plan.close()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("separate", [False, True])
+def test_full_mixed_order_rk3_step(sv, oracle_mod, c4, dtype, separate):
+    """One SSP-RK3 step (dt = 1e-3) of the full mixed-order workload from the
+    autotuned graph, against the oracle's step, on every element."""
+    cast = (lambda a: a) if dtype == torch.float64 else (lambda a: np.asarray(a, np.float32))
+    sizes = [w.q.size for w in c4]
+    q0 = np.concatenate([cast(w.q).ravel() for w in c4])
+    q_n = torch.from_numpy(q0).cuda()
+    q_1, q_2, L = (torch.empty_like(q_n) for _ in range(3))
+    blocks, off = [], 0
+    for w, sz in zip(c4, sizes):
+        blocks.append(dict(q=q_n[off:off + sz].view(w.q.shape), geo=dev(cast(w.geo)),
+                           D=dev(cast(w.D)), rho_ref=dev(cast(w.rho_ref)),
+                           theta_ref=dev(w.theta_ref), rhs=L[off:off + sz].view(w.q.shape)))
+        off += sz
+    dt = 1e-3
+    g = sv.RK3Graph(blocks, q_n, q_1, q_2, L, dt, c4[0].phys.as_tuple(), autotune=True,
+                    separate_stages=separate)
+    g.step()
+    got = host(q_n).astype(np.float64)
+    g.close()
+    off = 0
+    for w, sz in zip(c4, sizes):
+        src = w if dtype == torch.float64 else I.upcast(I.to_fp32(w))
+        rate = lambda qq, src=src: oracle_mod.volume_rhs(src.D, src.geo, qq, src.rho_ref,
+                                                         src.theta_ref, src.phys.as_tuple())
+        r = oracle_mod.ssp_rk3_step(rate, src.q, dt)
+        qa = got[off:off + sz].reshape(w.q.shape)
+        e = err(qa - src.q, r - src.q)
+        assert e.max() <= (1e-10 if dtype == torch.float64 else 1e-3), (w.N, e)
+        off += sz
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("Nq", [4, 8, 12, 16])
+def test_full_table2_shapes(sv, oracle_mod, Nq):
+    """The paper-comparable configuration at its full Table 2 size (3,538,944
+    nodes, 8 fields, FP32, accumulated), r+s and r+s+t."""
+    phys = (1.0, 1.4, 1.0, 0.0)
+    w32 = I.to_fp32(I.table2_workload(Nq))
+    u = I.upcast(w32)
+    base = np.random.default_rng(Nq).standard_normal(w32.q.shape).astype(np.float32)
+    q, geo, D = dev(w32.q), dev(w32.geo), dev(w32.D)
+    for dirs in (3, 7):
+        ref = oracle_mod.volume_rhs_ext(u.D, u.geo, u.q, None, None, phys, dirs=dirs,
+                                        out=base.astype(np.float64), accumulate=True)
+        out = dev(base.copy())
+        sv.volume_rhs_ext(q, geo, D, None, None, phys, dirs=dirs, out=out, accumulate=True)
+        e = err(host(out), ref)
+        assert e.max() <= TOL32, (Nq, dirs, e)
+
+
+@pytest.mark.slow
+def test_full_ladder_table1_shape(sv, oracle_mod):
+    """Every ladder level at the Nq = 8 Table 2 shape (6912 elements)."""
+    phys = (1.0, 1.4, 1.0, 0.0)
+    w32 = I.to_fp32(I.table2_workload(8))
+    u = I.upcast(w32)
+    base = np.random.default_rng(8).standard_normal(w32.q.shape).astype(np.float32)
+    ref = oracle_mod.volume_rhs_ext(u.D, u.geo, u.q, None, None, phys, dirs=3,
+                                    out=base.astype(np.float64), accumulate=True)
+    q, geo, D = dev(w32.q), dev(w32.geo), dev(w32.D)
+    for level in range(1, sv.LADDER_LEVELS + 1):
+        out = dev(base.copy())
+        sv.volume_rhs_ladder(level, q, geo, D, phys, out=out)
+        e = err(host(out), ref)
+        assert e.max() <= TOL32, (level, e)
+
+
+@pytest.mark.slow
+def test_full_affine_per_element_n7(sv, oracle_mod):
+    """Per-element metric terms on 32768 affine N=7 elements (FP64 and FP32)."""
+    w = I.affine_workload(N=7, n_side=32, k=1, with_adjoint=False)
+    phys = w.phys.as_tuple()
+    ref = oracle_mod.volume_rhs(w.D, w.geo, w.q, w.rho_ref, w.theta_ref, phys)
+    out = sv.volume_rhs_affine(dev(w.q), dev(I.element_geo(w.geo)), dev(w.D), dev(w.rho_ref),
+                               dev(w.theta_ref), phys)
+    assert err(host(out), ref).max() <= TOL64
+    del out
+    w32 = I.to_fp32(w)
+    u = I.upcast(w32)
+    ref32 = oracle_mod.volume_rhs(u.D, u.geo, u.q, u.rho_ref, u.theta_ref, phys)
+    out32 = sv.volume_rhs_affine(dev(w32.q), dev(I.element_geo(w32.geo)), dev(w32.D),
+                                 dev(w32.rho_ref), dev(w32.theta_ref), phys)
+    assert err(host(out32), ref32).max() <= TOL32
