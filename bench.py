@@ -51,10 +51,10 @@ def flops_per_node(Nq: int) -> int:
     return 30 * Nq + 63
 
 
-# Sources that define the single-order volume kernels (the ones the
-# roofline's traffic figure describes).
+# Sources that define the kernels whose measured traffic is recorded (the
+# single-order volume and adjoint kernels and the extended kernels).
 VOLUME_KERNEL_SOURCES = ("sem_device.hpp", "sem_internal.hpp", "kernels.inc", "kernels_f64.hip",
-                         "kernels_f32.hip")
+                         "kernels_f32.hip", "ext.inc", "ext_f64.hip", "ext_f32.hip")
 
 
 def kernel_source_hash() -> str:
@@ -73,10 +73,10 @@ def measured_traffic(kernel_key: str):
         d = json.load(open(p))
     except (OSError, ValueError):
         return None
-    ent = d.get(kernel_key)
-    if not ent or ent.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash():
         return None
-    return ent.get("bytes_per_launch")
+    ent = d.get("kernels", {}).get(kernel_key)
+    return ent.get("bytes_per_launch") if ent else None
 
 
 def time_launches(fn, steps: int, warmup: int, stream):
