@@ -142,7 +142,7 @@ ladder_kernel(const float* D, const float* geo, const float* q, float* rhs, Phys
                     }
 #pragma unroll
                     for (int b = 0; b < NF; ++b)
-                        re[b * M] -= LEVEL == 4 ? acc[b] : jinv * acc[b];
+                        re[b * M + m] -= LEVEL == 4 ? acc[b] : jinv * acc[b];
                 }
             }
             __syncthreads();   // sF is rewritten by the next slice
