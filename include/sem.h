@@ -142,9 +142,11 @@ int32_t sem_tile_options(sem_dtype dtype, int32_t Nq, sem_tile* out, int32_t cap
  *             q, rhs: [Ne][nfields][Nq^3]
  *   dirs      SEM_DIR_R | SEM_DIR_S, or SEM_DIR_R | SEM_DIR_S | SEM_DIR_T; the
  *             geo slots of an excluded direction are not read
- *   Nq        2..10, 12 or 16 (in FP64, Nq = 16 does not fit the 160 KB LDS)
+ *   Nq        2..10, 12 or 16 (in FP64, Nq = 16 with r+s+t does not fit the
+ *             160 KB LDS)
  * All other arguments, the gravity source and the reference state are as for
- * sem_volume_rhs.  Each (Nq, nfields, dirs) has one built-in tile shape.
+ * sem_volume_rhs.  Each (Nq, nfields, dirs) has one built-in tile shape; r+s at
+ * Nq >= 12 walks each element a k-slice at a time.
  * Errors: unsupported nfields / dirs / Nq -> SEM_ERR_UNSUPPORTED; otherwise as
  * sem_volume_rhs.  Allocates nothing.
  */
