@@ -250,7 +250,7 @@ struct RkNode<T, true> {
 
 // Epilogue for one node: rhs = -(1/J) acc + source (+ rhs when ACC), or the
 // fused Runge-Kutta stage out = a x + b (q + dt v) when RK (five fields).
-template <typename T, int M, int NF, bool ACC, bool RK>
+template <typename T, int M, int NF, bool ACC, bool RK, bool STREAM = true>
 __device__ __forceinline__ void store_node(const BlockPtrs<T>& B, const RkStage& rk, int64_t e,
                                            int m, const T (&acc)[NF], T jinv, T src,
                                            const RkNode<T, RK>& rn)
@@ -264,10 +264,14 @@ __device__ __forceinline__ void store_node(const BlockPtrs<T>& B, const RkStage&
             v += src;
         if constexpr (RK) {
             st_stream(re + b * M, (T)rk.a * rn.x[b] + (T)rk.b * (rn.q[b] + (T)rk.dt * v));
-        } else {
+        } else if constexpr (STREAM) {
             if constexpr (ACC)
                 v += ld_stream(re + b * M);
             st_stream(re + b * M, v);
+        } else {
+            if constexpr (ACC)
+                v += re[b * M];
+            re[b * M] = v;
         }
     }
 }
@@ -283,8 +287,10 @@ struct NodeState {
 };
 
 // GEOE: the metric terms are given once per element (affine elements,
-// geo[e][10]) instead of at every node (geo[e][10][Nq^3]).
-template <typename T, int M, int NF, int DIRS, bool GEOE = false>
+// geo[e][10]) instead of at every node (geo[e][10][Nq^3]).  STREAM = false
+// reads through the cache (for tiles whose consecutive accesses share cache
+// lines).
+template <typename T, int M, int NF, int DIRS, bool GEOE = false, bool STREAM = true>
 __device__ __forceinline__ void load_node(const BlockPtrs<T>& B, const Phys& ph, int64_t e, int m,
                                           NodeState<T, NF>& st)
 {
@@ -293,16 +299,17 @@ __device__ __forceinline__ void load_node(const BlockPtrs<T>& B, const Phys& ph,
     const T* __restrict__ ge = GEOE ? B.geo + e * 10 : B.geo + e * (10 * M) + m;
     // per-element metric records are shared by every node of the element and
     // stay cached; everything else streams
-    auto geo_at = [&](int s) { return GEOE ? ge[s * GS] : ld_stream(ge + s * GS); };
-    const T rho = ld_stream(qe);
+    auto ld = [](const auto* p) { return STREAM ? ld_stream(p) : *p; };
+    auto geo_at = [&](int s) { return GEOE ? ge[s * GS] : ld(ge + s * GS); };
+    const T rho = ld(qe);
     st.rho = rho;
-    st.U1 = ld_stream(qe + M);
-    st.U2 = ld_stream(qe + 2 * M);
-    st.U3 = ld_stream(qe + 3 * M);
-    st.Th = ld_stream(qe + 4 * M);
+    st.U1 = ld(qe + M);
+    st.U2 = ld(qe + 2 * M);
+    st.U3 = ld(qe + 3 * M);
+    st.Th = ld(qe + 4 * M);
 #pragma unroll
     for (int b = 5; b < NF; ++b)
-        st.Q[b - 5] = ld_stream(qe + b * M);
+        st.Q[b - 5] = ld(qe + b * M);
 #pragma unroll
     for (int s = 0; s < 9; ++s)
         st.g[s] = ((DIRS >> (s / 3)) & 1) ? geo_at(s) : (T)0;
@@ -311,8 +318,8 @@ __device__ __forceinline__ void load_node(const BlockPtrs<T>& B, const Phys& ph,
     T rr = (T)0;
     double thr = 0.0;
     if (has_ref) {
-        rr = ld_stream(B.rho_ref + e * M + m);
-        thr = ld_stream(B.theta_ref + e * M + m);
+        rr = ld(B.rho_ref + e * M + m);
+        thr = ld(B.theta_ref + e * M + m);
     }
     st.src = -(T)ph.grav * (rho - rr);
     st.pp = Pressure<T>::eval(st.Th, has_ref, thr, ph);
@@ -566,6 +573,9 @@ __device__ __forceinline__ void volume_tile_slab(const BlockPtrs<T>& B, int64_t 
     constexpr int M = Shape<NQ>::M;
     constexpr int NT = slab_threads<NQ>();
     constexpr int BUF = 2 * NF * NQ2;   // one slice: r and s fluxes of every field
+    // a slice row that is not a whole number of 128-byte lines shares a line
+    // with the next slice, which a cached read then serves
+    constexpr bool STREAM = (NQ2 * (int)sizeof(T)) % 128 == 0;
     T* __restrict__ sD = smem;
     T* __restrict__ sF = smem + Shape<NQ>::template d_slots<T>();
     const int tid = threadIdx.x;
@@ -583,13 +593,14 @@ __device__ __forceinline__ void volume_tile_slab(const BlockPtrs<T>& B, int64_t 
             acc[b] = (T)0;
         contract<T, NQ, NQ2, NF>(sD, F + NQ * j, i, 1, acc);
         contract<T, NQ, NQ2, NF>(sD, F + NF * NQ2 + i, j, NQ, acc);
-        store_node<T, M, NF, ACC, false>(B, no_rk, e, tid + NQ2 * k, acc, st.jinv, st.src, no_rn);
+        store_node<T, M, NF, ACC, false, STREAM>(B, no_rk, e, tid + NQ2 * k, acc, st.jinv, st.src,
+                                                 no_rn);
     };
 
     if constexpr (DB) {
         NodeState<T, NF> st;
         if (live)
-            load_node<T, M, NF, 3, GEOE>(B, ph, e, tid, st);
+            load_node<T, M, NF, 3, GEOE, STREAM>(B, ph, e, tid, st);
 #pragma unroll 1
         for (int k = 0; k < NQ; ++k) {
             T* __restrict__ F = sF + (k & 1) * BUF;
@@ -602,7 +613,7 @@ __device__ __forceinline__ void volume_tile_slab(const BlockPtrs<T>& B, int64_t 
             __syncthreads();
             NodeState<T, NF> nx;
             if (live && k + 1 < NQ)
-                load_node<T, M, NF, 3, GEOE>(B, ph, e, tid + NQ2 * (k + 1), nx);
+                load_node<T, M, NF, 3, GEOE, STREAM>(B, ph, e, tid + NQ2 * (k + 1), nx);
             if (live)
                 contract_slice(F, st, k);
             if (k + 1 < NQ)
@@ -613,7 +624,7 @@ __device__ __forceinline__ void volume_tile_slab(const BlockPtrs<T>& B, int64_t 
         for (int k = 0; k < NQ; ++k) {
             NodeState<T, NF> st;
             if (live) {
-                load_node<T, M, NF, 3, GEOE>(B, ph, e, tid + NQ2 * k, st);
+                load_node<T, M, NF, 3, GEOE, STREAM>(B, ph, e, tid + NQ2 * k, st);
                 put_flux<T, NQ2, NF>(st, 0, sF + tid);
                 put_flux<T, NQ2, NF>(st, 1, sF + NF * NQ2 + tid);
             }
