@@ -283,7 +283,19 @@ benchmark kernel (levels 1-6) at Nq = 8 on the Table 2 shape.
     return out
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, budget_s: float):
+    """The FP64 oracle on the host cores (all of them, then one) over the same
+    N=7 workload: a reported baseline, not a target."""
     import oracle
     phys = w.phys.as_tuple()
     out = np.empty_like(w.q)
@@ -295,10 +307,26 @@ def cpu_baseline(w, budget_s: float):
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
-    return {"value": n * w.Ne / el, "unit": "elements/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
+    cores = oracle.max_threads()
+    # one core, on a 2048-element slice, for a short fixed budget
+    oracle.set_threads(1)
+    try:
+        n1, t1 = 0, time.perf_counter()
+        while True:
+            oracle.volume_rhs(w.D, w.geo, w.q, w.rho_ref, w.theta_ref, phys, out=out,
+                              elements=(0, 2048))
+            n1 += 1
+            el1 = time.perf_counter() - t1
+            if el1 >= min(3.0, budget_s):
+                break
+    finally:
+        oracle.set_threads(cores)
+    return {"value": n * w.Ne / el, "unit": "elements/s", "cores": cores,
+            "kind": "oracle", "cpu_model": _cpu_model(),
+            "value_1core": n1 * 2048 / el1,
             "sample": f"FP64 oracle over the full N=7 warped mesh ({w.Ne} elements), "
-                      f"{n} passes in {el:.1f} s"}
+                      f"{n} passes in {el:.1f} s on {cores} threads; 1 thread: {n1} passes over "
+                      f"the first 2048 elements in {el1:.1f} s"}
 
 
 def main(argv=None):
