@@ -5,6 +5,8 @@ field): FP64 forward <= 1e-12, FP32 forward <= 2e-5 (oracle on the
 FP32-rounded inputs, upcast exactly, with the shared FP64 Theta_ref), FP64
 adjoint <= 1e-7 (expected ~1e-14), FP32 adjoint <= 2e-5.
 """
+import json
+
 import numpy as np
 import pytest
 import torch
@@ -260,6 +262,32 @@ def test_batch_mixed_order(sv, oracle_mod, dtype, autotune):
         e = err(host(b["rhs"]), oracle_fwd(oracle_mod, src))
         assert e.max() <= (TOL64 if dtype == torch.float64 else TOL32), (w.N, e)
     plan.close()
+
+
+def test_batch_plan_cache_round_trip(sv, oracle_mod, tmp_path, monkeypatch):
+    """Tuned shapes are written to the file named by SEM_PLAN_CACHE and read
+    back by the next plan; an unreadable file is ignored and rewritten."""
+    path = tmp_path / "plans.json"
+    path.write_text("not a plan cache")
+    monkeypatch.setenv("SEM_PLAN_CACHE", str(path))
+    ws = I.mixed_order_workloads(orders=(3, 5), per_order=40, k=81)
+    blocks = _batch(ws, torch.float64)
+    phys = ws[0].phys.as_tuple()
+    p1 = sv.BatchPlan(blocks, phys, autotune=True, use_cache=True)
+    d1 = p1.describe()
+    p1.close()
+    assert d1["autotuned"] and not d1["from_cache"]
+    keys = json.loads(path.read_text())
+    assert keys and all("/f64/" in k for k in keys)
+    p2 = sv.BatchPlan(blocks, phys, autotune=True, use_cache=True)
+    d2 = p2.describe()
+    assert d2["from_cache"]
+    shape = lambda d: [(o["Nq"], o["elems_per_block"], o["layout"]) for o in d["orders"]]
+    assert shape(d2) == shape(d1) and d2["threads"] == d1["threads"]
+    p2.execute()
+    for w, b in zip(ws, blocks):
+        assert err(host(b["rhs"]), oracle_fwd(oracle_mod, w)).max() <= TOL64
+    p2.close()
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
