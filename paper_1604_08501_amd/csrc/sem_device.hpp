@@ -655,6 +655,14 @@ struct AdjPtrs {
     int64_t Ne;
 };
 
+// Pointwise inputs of one adjoint node, read in phase 1 together with lambda
+// so that every global load of the tile is in flight before the barrier.
+template <typename T>
+struct AdjNode {
+    T U1, U2, U3, Th, rinv, dpdT, lam3;
+    T g[9];
+};
+
 template <typename T, int NQ, int EPB, int NT, bool ACC>
 __device__ __forceinline__ void adjoint_tile(const AdjPtrs<T>& B, int64_t e0, int ne,
                                              const Phys& ph, T* __restrict__ smem)
@@ -670,7 +678,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjPtrs<T>& B, int64_t e0, in
     for (int x = tid; x < NQ2; x += NT)
         sD[x] = B.D[x];
 
-    T lam3[NPT];
+    AdjNode<T> nd[NPT];
 #pragma unroll
     for (int p = 0; p < NPT; ++p) {
         const int t = tid + p * NT;
@@ -679,15 +687,28 @@ __device__ __forceinline__ void adjoint_tile(const AdjPtrs<T>& B, int64_t e0, in
         if (t < NODES && es < ne) {
             const int64_t e = e0 + es;
             const T* __restrict__ le = B.lambda + e * (5 * M) + m;
-            const T jinv = ld_stream(B.geo + e * (10 * M) + 9 * M + m);
+            const T* __restrict__ qe = B.q + e * (5 * M) + m;
+            const T* __restrict__ ge = B.geo + e * (10 * M) + m;
+            T lb[5];
+#pragma unroll
+            for (int b = 0; b < 5; ++b)
+                lb[b] = ld_stream(le + b * M);
+            const T jinv = ld_stream(ge + 9 * M);
+            const T rho = ld_stream(qe);
+            nd[p].U1 = ld_stream(qe + M);
+            nd[p].U2 = ld_stream(qe + 2 * M);
+            nd[p].U3 = ld_stream(qe + 3 * M);
+            nd[p].Th = ld_stream(qe + 4 * M);
+#pragma unroll
+            for (int s = 0; s < 9; ++s)
+                nd[p].g[s] = ld_stream(ge + s * M);
             T* W = sW + es * (5 * M) + m;
 #pragma unroll
-            for (int b = 0; b < 5; ++b) {
-                const T lb = ld_stream(le + b * M);
-                if (b == 3)
-                    lam3[p] = lb;
-                W[b * M] = -jinv * lb;
-            }
+            for (int b = 0; b < 5; ++b)
+                W[b * M] = -jinv * lb[b];
+            nd[p].lam3 = lb[3];
+            nd[p].rinv = (T)1 / rho;
+            nd[p].dpdT = Pressure<T>::dp_dtheta(nd[p].Th, ph);
         }
     }
     __syncthreads();
@@ -702,14 +723,7 @@ __device__ __forceinline__ void adjoint_tile(const AdjPtrs<T>& B, int64_t e0, in
             const int j = (m / NQ) % NQ;
             const int k = m / NQ2;
             const int64_t e = e0 + es;
-            const T* __restrict__ qe = B.q + e * (5 * M) + m;
-            const T* __restrict__ ge = B.geo + e * (10 * M) + m;
-            const T rho = ld_stream(qe), U1 = ld_stream(qe + M), U2 = ld_stream(qe + 2 * M);
-            const T U3 = ld_stream(qe + 3 * M), Th = ld_stream(qe + 4 * M);
-            T g[9];
-#pragma unroll
-            for (int s = 0; s < 9; ++s)
-                g[s] = ld_stream(ge + s * M);
+            const AdjNode<T>& n = nd[p];
             const T* __restrict__ We = sW + es * (5 * M);
             T G[3][5];
 #pragma unroll
@@ -747,22 +761,20 @@ __device__ __forceinline__ void adjoint_tile(const AdjPtrs<T>& B, int64_t e0, in
                         G[2][b] += dx * Wt[b * M + NQ2 * x];
                 }
             }
-            const T rinv = (T)1 / rho;
-            const T dpdT = Pressure<T>::dp_dtheta(Th, ph);
             T mu0 = (T)0, mu1 = (T)0, mu2 = (T)0, mu3 = (T)0, mu4 = (T)0;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const T g1 = g[3 * d], g2 = g[3 * d + 1], g3 = g[3 * d + 2];
-                const T vd = (g1 * U1 + g2 * U2 + g3 * U3) * rinv;
-                const T Ad = G[d][1] * U1 + G[d][2] * U2 + G[d][3] * U3 + G[d][4] * Th;
-                const T cd = G[d][0] + Ad * rinv;
+                const T g1 = n.g[3 * d], g2 = n.g[3 * d + 1], g3 = n.g[3 * d + 2];
+                const T vd = (g1 * n.U1 + g2 * n.U2 + g3 * n.U3) * n.rinv;
+                const T Ad = G[d][1] * n.U1 + G[d][2] * n.U2 + G[d][3] * n.U3 + G[d][4] * n.Th;
+                const T cd = G[d][0] + Ad * n.rinv;
                 mu0 += vd * Ad;
                 mu1 += g1 * cd + vd * G[d][1];
                 mu2 += g2 * cd + vd * G[d][2];
                 mu3 += g3 * cd + vd * G[d][3];
-                mu4 += dpdT * (g1 * G[d][1] + g2 * G[d][2] + g3 * G[d][3]) + vd * G[d][4];
+                mu4 += n.dpdT * (g1 * G[d][1] + g2 * G[d][2] + g3 * G[d][3]) + vd * G[d][4];
             }
-            mu0 = -rinv * mu0 - (T)ph.grav * lam3[p];
+            mu0 = -n.rinv * mu0 - (T)ph.grav * n.lam3;
             T* __restrict__ me = B.mu + e * (5 * M) + m;
             const T out[5] = {mu0, mu1, mu2, mu3, mu4};
 #pragma unroll
@@ -774,7 +786,6 @@ __device__ __forceinline__ void adjoint_tile(const AdjPtrs<T>& B, int64_t e0, in
             }
         }
     }
-    __syncthreads();
 }
 
 }  // namespace semk
