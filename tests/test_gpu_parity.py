@@ -576,3 +576,24 @@ def test_full_affine_per_element_n7(sv, oracle_mod):
     out32 = sv.volume_rhs_affine(dev(w32.q), dev(I.element_geo(w32.geo)), dev(w32.D),
                                  dev(w32.rho_ref), dev(w32.theta_ref), phys)
     assert err(host(out32), ref32).max() <= TOL32
+
+
+@pytest.mark.slow
+def test_indices_beyond_2_31(sv, oracle_mod):
+    """FP32 at N=7 with 425,000 elements: the metric array holds 2.18e9 values
+    (more than 2^31), so any 32-bit index arithmetic would show up in the last
+    elements.  The mesh is 1000 warped elements repeated on the device."""
+    base = I.to_fp32(I.warped_workload(N=7, n_elements=1000, k=170))
+    ref = oracle_fwd(oracle_mod, I.upcast(base))
+    reps = 425
+    q = dev(base.q).repeat(reps, 1, 1)
+    geo = dev(base.geo).repeat(reps, 1, 1)
+    assert geo.numel() > 2 ** 31
+    rr = dev(base.rho_ref).repeat(reps, 1)
+    tr = dev(base.theta_ref).repeat(reps, 1)
+    out = sv.volume_rhs(q, geo, dev(base.D), rr, tr, base.phys.as_tuple())
+    for lo in (0, 212 * 1000, (reps - 1) * 1000):
+        got = host(out[lo:lo + 1000])
+        assert err(got, ref).max() <= TOL32, lo
+    del q, geo, rr, tr, out
+    torch.cuda.empty_cache()
