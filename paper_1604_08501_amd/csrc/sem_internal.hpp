@@ -7,7 +7,8 @@
 #include "sem_device.hpp"
 
 // Compiled tile shapes (Nq, elements per workgroup, layout).  The
-// single-order kernels use ceil64(EPB * Nq^3) threads (one node per thread);
+// single-order kernels use ceil64(EPB * Nq^3) threads (one node per thread;
+// 512 threads with two nodes each for aliased tiles of more than 512 nodes);
 // the mixed-order batch kernel runs every shape with a fixed workgroup size.
 // Layout 0 keeps all three directions' fluxes in LDS, layout 1 one direction
 // at a time.
