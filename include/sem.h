@@ -85,7 +85,10 @@ typedef struct sem_phys {
  * layout.  SEM_LAYOUT_FULL stages the contravariant fluxes of all three
  * reference directions in LDS (one barrier); SEM_LAYOUT_ALIAS stages one
  * direction at a time (a third of the LDS, three barriers).  Zeros select the
- * built-in default for (dtype, Nq). */
+ * built-in default for (dtype, Nq), the fastest compiled shape measured on
+ * MI355X; a zero element count with an explicit layout takes the default's
+ * count when that shape exists (else the smallest compiled one), and an
+ * explicit count with SEM_LAYOUT_DEFAULT takes FULL if compiled, else ALIAS. */
 #define SEM_LAYOUT_DEFAULT 0
 #define SEM_LAYOUT_FULL 1
 #define SEM_LAYOUT_ALIAS 2
