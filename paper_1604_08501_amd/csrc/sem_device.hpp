@@ -474,7 +474,6 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
     constexpr int NPT = nodes_per_thread<NQ, EPB, NT>();
     static_assert(NPT <= alias_max_nodes_per_thread<T>(),
                   "ALIAS tiles keep every node's state of a thread in registers");
-    static_assert(!RK || NPT == 1, "a fused Runge-Kutta stage needs one node per thread");
     T* __restrict__ sD = smem;
     T* __restrict__ sF = smem + Shape<NQ>::template d_slots<T>();
     const int tid = threadIdx.x;

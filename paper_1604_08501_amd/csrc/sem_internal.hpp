@@ -85,7 +85,8 @@ struct Tile {
     int32_t pad;
     int64_t e0;
 };
-// rk: the shape must also run a fused Runge-Kutta stage (one node per thread)
+// rk: the shape must also run a fused Runge-Kutta stage (one node per thread
+// for FULL, at most two for ALIAS)
 template <typename T>
 bool batch_variant_ok(int nt, int nq, int epb, int lay, bool rk);
 template <typename T>
