@@ -549,8 +549,7 @@ __device__ __forceinline__ void volume_tile(const BlockPtrs<T>& B, int64_t e0, i
 // kernel).  The r and s contractions of slice k need only slice k's fluxes,
 // so the LDS holds 2 NF Nq^2 values instead of the whole element's, which
 // keeps large elements (Nq = 12, 16) resident several workgroups per CU and
-// fits FP64 at Nq = 16.  DB: two slice buffers, one barrier per slice, and the
-// next slice's state is loaded before the current slice's contractions.
+// fits FP64 at Nq = 16.
 // ---------------------------------------------------------------------------
 template <int NQ>
 constexpr int slab_threads()
@@ -558,20 +557,19 @@ constexpr int slab_threads()
     return ((NQ * NQ + 63) / 64) * 64;
 }
 
-template <typename T, int NQ, int NF, bool DB>
+template <typename T, int NQ, int NF>
 constexpr int volume_slab_lds_values()
 {
-    return Shape<NQ>::template d_slots<T>() + (DB ? 2 : 1) * 2 * NF * NQ * NQ;
+    return Shape<NQ>::template d_slots<T>() + 2 * NF * NQ * NQ;
 }
 
-template <typename T, int NQ, bool ACC, int NF, bool DB, bool GEOE>
+template <typename T, int NQ, bool ACC, int NF, bool GEOE>
 __device__ __forceinline__ void volume_tile_slab(const BlockPtrs<T>& B, int64_t e, const Phys& ph,
                                                  T* __restrict__ smem)
 {
     constexpr int NQ2 = Shape<NQ>::NQ2;
     constexpr int M = Shape<NQ>::M;
     constexpr int NT = slab_threads<NQ>();
-    constexpr int BUF = 2 * NF * NQ2;   // one slice: r and s fluxes of every field
     // a slice row that is not a whole number of 128-byte lines shares a line
     // with the next slice, which a cached read then serves
     constexpr bool STREAM = (NQ2 * (int)sizeof(T)) % 128 == 0;
@@ -584,54 +582,26 @@ __device__ __forceinline__ void volume_tile_slab(const BlockPtrs<T>& B, int64_t 
     const int i = tid % NQ, j = tid / NQ;
     const RkStage no_rk{0.0, 0.0, 0.0};
     const RkNode<T, false> no_rn{};
-
-    auto contract_slice = [&](const T* __restrict__ F, const NodeState<T, NF>& st, int k) {
-        T acc[NF];
-#pragma unroll
-        for (int b = 0; b < NF; ++b)
-            acc[b] = (T)0;
-        contract<T, NQ, NQ2, NF>(sD, F + NQ * j, i, 1, acc);
-        contract<T, NQ, NQ2, NF>(sD, F + NF * NQ2 + i, j, NQ, acc);
-        store_node<T, M, NF, ACC, false, STREAM>(B, no_rk, e, tid + NQ2 * k, acc, st.jinv, st.src,
-                                                 no_rn);
-    };
-
-    if constexpr (DB) {
+#pragma unroll 1
+    for (int k = 0; k < NQ; ++k) {
         NodeState<T, NF> st;
-        if (live)
-            load_node<T, M, NF, 3, GEOE, STREAM>(B, ph, e, tid, st);
-#pragma unroll 1
-        for (int k = 0; k < NQ; ++k) {
-            T* __restrict__ F = sF + (k & 1) * BUF;
-            if (live) {
-                put_flux<T, NQ2, NF>(st, 0, F + tid);
-                put_flux<T, NQ2, NF>(st, 1, F + NF * NQ2 + tid);
-            }
-            // (every lane's reads of this buffer, two slices ago, came before
-            // the previous slice's barrier, so one barrier per slice suffices)
-            __syncthreads();
-            NodeState<T, NF> nx;
-            if (live && k + 1 < NQ)
-                load_node<T, M, NF, 3, GEOE, STREAM>(B, ph, e, tid + NQ2 * (k + 1), nx);
-            if (live)
-                contract_slice(F, st, k);
-            if (k + 1 < NQ)
-                st = nx;
+        if (live) {
+            load_node<T, M, NF, 3, GEOE, STREAM>(B, ph, e, tid + NQ2 * k, st);
+            put_flux<T, NQ2, NF>(st, 0, sF + tid);
+            put_flux<T, NQ2, NF>(st, 1, sF + NF * NQ2 + tid);
         }
-    } else {
-#pragma unroll 1
-        for (int k = 0; k < NQ; ++k) {
-            NodeState<T, NF> st;
-            if (live) {
-                load_node<T, M, NF, 3, GEOE, STREAM>(B, ph, e, tid + NQ2 * k, st);
-                put_flux<T, NQ2, NF>(st, 0, sF + tid);
-                put_flux<T, NQ2, NF>(st, 1, sF + NF * NQ2 + tid);
-            }
-            __syncthreads();
-            if (live)
-                contract_slice(sF, st, k);
-            __syncthreads();   // the slice buffer is rewritten by the next slice
+        __syncthreads();
+        if (live) {
+            T acc[NF];
+#pragma unroll
+            for (int b = 0; b < NF; ++b)
+                acc[b] = (T)0;
+            contract<T, NQ, NQ2, NF>(sD, sF + NQ * j, i, 1, acc);
+            contract<T, NQ, NQ2, NF>(sD, sF + NF * NQ2 + i, j, NQ, acc);
+            store_node<T, M, NF, ACC, false, STREAM>(B, no_rk, e, tid + NQ2 * k, acc, st.jinv, st.src,
+                                                     no_rn);
         }
+        __syncthreads();   // the slice buffer is rewritten by the next slice
     }
 }
 
