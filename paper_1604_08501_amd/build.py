@@ -26,7 +26,7 @@ SOURCES = [
     "ext_f64.hip", "ext_f32.hip", "ladder.hip",
     "batch_f64.hip", "batch_f32.hip",
     "kernels_f64.hip", "kernels_f32.hip",
-    "sem_api.cpp",
+    "sem_api.cpp", "sem_plan.cpp",
 ]
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

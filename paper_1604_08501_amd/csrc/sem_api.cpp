@@ -1,27 +1,26 @@
-// C-ABI of libsem.so: argument validation, status codes, tile selection,
-// batch plans (autotuner, plan cache, device tile tables) and the SSP-RK3
-// step captured in a HIP graph.  The operations themselves are documented
-// in include/sem.h; the kernels live in kernels_*.hip and batch_*.hip.
+// C-ABI of libsem.so, single-order entry points: argument validation, status
+// codes, tile selection and the launches of the volume, extended, affine,
+// ladder, adjoint and axpby kernels.  Batch plans and the RK3 graph are in
+// sem_plan.cpp.  The operations themselves are documented in include/sem.h.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
-#include <cerrno>
-#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <map>
-#include <mutex>
 #include <string>
-#include <vector>
 
 #include "sem.h"
+#include "sem_host.hpp"
 #include "sem_internal.hpp"
 
-namespace {
+namespace semapi {
 
+namespace {
 thread_local std::string g_last_error;
+}  // namespace
+
+const char* last_error() { return g_last_error.c_str(); }
 
 sem_status fail(sem_status st, const char* fmt, ...)
 {
@@ -58,10 +57,9 @@ semk::Phys to_phys(const sem_phys* p)
     return semk::Phys{p->p0, p->gamma, p->R, p->grav, p->R / p->p0};
 }
 
-constexpr int kMinNq = 2, kMaxNq = 10;
-
-// Built-in tile shapes for the single-order kernels: about 256 threads for
-// small orders, one element per workgroup from Nq = 6 on, all fluxes in LDS.
+// Element counts of the small-order shapes with all fluxes resident: the
+// batch's fallback when a default tile does not fit its launch, and the
+// adjoint's tile.
 int default_epb(int nq)
 {
     switch (nq) {
@@ -74,14 +72,8 @@ int default_epb(int nq)
 }
 
 // public layout code (sem_tile.layout) -> internal layout, -1 if unknown
-// Built-in single-order tile per (dtype, Nq): the fastest compiled shape
-// measured on MI355X at about 1 GB per launch (every shape moves the same
-// bytes; they differ in occupancy and barrier count).
-struct DefaultTile {
-    int epb;
-    int lay;
-};
-
+// Every shape moves the same bytes; they differ in occupancy and barrier
+// count.
 DefaultTile default_tile(sem_dtype dt, int nq)
 {
     const bool f64 = dt == SEM_F64;
@@ -138,7 +130,7 @@ sem_status check_order(int32_t Ne, int32_t Nq)
     return SEM_OK;
 }
 
-sem_status check_ptr(const void* p, size_t align, const char* name, bool required = true)
+sem_status check_ptr(const void* p, size_t align, const char* name, bool required)
 {
     if (!p)
         return required ? fail(SEM_ERR_INVALID_ARG, "%s is NULL", name) : SEM_OK;
@@ -147,14 +139,6 @@ sem_status check_ptr(const void* p, size_t align, const char* name, bool require
     return SEM_OK;
 }
 
-#define SEM_TRY(expr)                 \
-    do {                              \
-        sem_status _st = (expr);      \
-        if (_st != SEM_OK)            \
-            return _st;               \
-    } while (0)
-
-// Pointers, alignment, the reference pair and aliasing of a volume-term call.
 sem_status check_volume_ptrs(sem_dtype dt, const void* D, const void* geo, const void* q,
                              const void* rho_ref, const double* theta_ref, const sem_phys* phys,
                              const void* rhs)
@@ -184,15 +168,11 @@ sem_status check_volume_args(int32_t Ne, int32_t Nq, sem_dtype dt, const void* D
     return check_volume_ptrs(dt, D, geo, q, rho_ref, theta_ref, phys, rhs);
 }
 
-template <typename T>
-semk::BlockPtrs<T> block_ptrs(int64_t Ne, const void* D, const void* geo, const void* q,
-                              const void* rho_ref, const double* theta_ref, void* rhs)
-{
-    return semk::BlockPtrs<T>{static_cast<const T*>(D),   static_cast<const T*>(geo),
-                              static_cast<const T*>(q),   static_cast<const T*>(rho_ref),
-                              theta_ref,                  static_cast<T*>(rhs),
-                              Ne,                         nullptr};
-}
+}  // namespace semapi
+
+using namespace semapi;
+
+namespace {
 
 int tile_options(int nq, sem_tile* out, int cap)
 {
@@ -211,7 +191,7 @@ int tile_options(int nq, sem_tile* out, int cap)
 // ===========================================================================
 // Single-order entry points
 // ===========================================================================
-extern "C" const char* sem_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char* sem_last_error(void) { return last_error(); }
 
 extern "C" const char* sem_version(void) { return "semvol 0.1.0 (gfx950)"; }
 
@@ -435,820 +415,3 @@ extern "C" sem_status sem_axpby(int64_t n, sem_dtype dtype, double a, const void
 // ===========================================================================
 // Batch plans
 // ===========================================================================
-namespace {
-
-struct OrderChoice {
-    int nq = 0;
-    int epb = 0;
-    int lay = semk::FULL;
-    double us = -1.0;        // measured time of this order alone (autotuned), else -1
-    int64_t elements = 0;
-};
-
-struct PlanCore {
-    sem_dtype dtype = SEM_F64;
-    semk::Phys phys{};
-    int nt = 256;
-    int lds_bytes = 0;
-    int ntiles = 0;
-    int device = 0;
-    bool rk = false;                    // fused Runge-Kutta stage epilogue
-    semk::RkStage rk_stage{0.0, 0.0, 0.0};
-    std::vector<sem_block> blocks;
-    std::vector<const void*> rk_x;      // per block, fused stage only
-    std::vector<OrderChoice> orders;    // one per distinct Nq
-    semh::Tile* d_tiles = nullptr;
-    void* d_blocks = nullptr;
-    bool autotuned = false;
-    bool from_cache = false;
-};
-
-void free_core(PlanCore* p)
-{
-    if (!p)
-        return;
-    if (p->d_tiles)
-        (void)hipFree(p->d_tiles);
-    if (p->d_blocks)
-        (void)hipFree(p->d_blocks);
-    p->d_tiles = nullptr;
-    p->d_blocks = nullptr;
-}
-
-sem_status check_block(const sem_block& b, int idx, sem_dtype dt, const sem_phys* phys)
-{
-    sem_status st = check_volume_args(b.Ne, b.Nq, dt, b.D, b.geo, b.q, b.rho_ref, b.theta_ref, phys,
-                                      b.rhs);
-    if (st != SEM_OK) {
-        std::string m = g_last_error;
-        return fail(st, "block %d: %s", idx, m.c_str());
-    }
-    return SEM_OK;
-}
-
-template <typename T>
-std::vector<semk::BatchBlock<T>> host_block_table(const PlanCore& p)
-{
-    std::vector<semk::BatchBlock<T>> v;
-    v.reserve(p.blocks.size());
-    for (size_t i = 0; i < p.blocks.size(); ++i) {
-        const sem_block& b = p.blocks[i];
-        semk::BlockPtrs<T> bp = block_ptrs<T>(b.Ne, b.D, b.geo, b.q, b.rho_ref, b.theta_ref, b.rhs);
-        if (p.rk)
-            bp.rk_x = static_cast<const T*>(p.rk_x[i]);
-        v.push_back(semk::BatchBlock<T>{bp, p.phys, p.rk_stage});
-    }
-    return v;
-}
-
-const OrderChoice& choice_for(const std::vector<OrderChoice>& orders, int nq)
-{
-    for (const OrderChoice& o : orders)
-        if (o.nq == nq)
-            return o;
-    return orders.front();   // unreachable: every block's order has a choice
-}
-
-// Tiles of every block whose order is in `only_nq` (all if 0), sorted by
-// decreasing estimated cost (longest-processing-time first, stable).
-std::vector<semh::Tile> make_tiles(const std::vector<sem_block>& blocks,
-                                   const std::vector<OrderChoice>& orders, int only_nq)
-{
-    struct Item {
-        semh::Tile t;
-        double cost;
-    };
-    std::vector<Item> items;
-    for (size_t bi = 0; bi < blocks.size(); ++bi) {
-        const sem_block& b = blocks[bi];
-        if (only_nq && b.Nq != only_nq)
-            continue;
-        const OrderChoice& oc = choice_for(orders, b.Nq);
-        const int vid = semh::variant_index(b.Nq, oc.epb, oc.lay);
-        const double nodes = (double)b.Nq * b.Nq * b.Nq;
-        // measured per-element time when autotuned, else a node count
-        const double per_elem = (oc.us > 0 && oc.elements > 0) ? oc.us / oc.elements : nodes;
-        for (int64_t e0 = 0; e0 < b.Ne; e0 += oc.epb) {
-            const int ne = (int)std::min<int64_t>(oc.epb, b.Ne - e0);
-            items.push_back({semh::Tile{(int32_t)bi, vid, ne, 0, e0}, per_elem * oc.epb});
-        }
-    }
-    std::stable_sort(items.begin(), items.end(),
-                     [](const Item& a, const Item& b) { return a.cost > b.cost; });
-    std::vector<semh::Tile> out;
-    out.reserve(items.size());
-    for (const Item& it : items)
-        out.push_back(it.t);
-    return out;
-}
-
-int shape_lds(sem_dtype dt, int nt, int nq, int epb, int lay)
-{
-    return dt == SEM_F64 ? semh::batch_lds_bytes<double>(nt, nq, epb, lay)
-                         : semh::batch_lds_bytes<float>(nt, nq, epb, lay);
-}
-
-int lds_for(sem_dtype dt, int nt, const std::vector<OrderChoice>& orders)
-{
-    int lds = 0;
-    for (const OrderChoice& o : orders)
-        lds = std::max(lds, shape_lds(dt, nt, o.nq, o.epb, o.lay));
-    return lds;
-}
-
-bool variant_ok(sem_dtype dt, int nt, int nq, int epb, int lay, bool rk)
-{
-    return dt == SEM_F64 ? semh::batch_variant_ok<double>(nt, nq, epb, lay, rk)
-                         : semh::batch_variant_ok<float>(nt, nq, epb, lay, rk);
-}
-
-hipError_t occupancy(sem_dtype dt, int nt, int lds, bool rk, int* bpc)
-{
-    return dt == SEM_F64 ? semh::batch_blocks_per_cu<double>(nt, lds, rk, bpc)
-                         : semh::batch_blocks_per_cu<float>(nt, lds, rk, bpc);
-}
-
-hipError_t launch(const PlanCore& p, const semh::Tile* d_tiles, int ntiles, int lds, hipStream_t s)
-{
-    if (p.dtype == SEM_F64)
-        return semh::launch_batch<double>(p.nt, d_tiles, ntiles,
-                                          static_cast<const semk::BatchBlock<double>*>(p.d_blocks),
-                                          p.rk, lds, s);
-    return semh::launch_batch<float>(p.nt, d_tiles, ntiles,
-                                     static_cast<const semk::BatchBlock<float>*>(p.d_blocks), p.rk,
-                                     lds, s);
-}
-
-// The batch kernel must fit at least one workgroup per CU with `lds` bytes.
-sem_status check_resident(const PlanCore& p, int lds)
-{
-    int bpc = 0;
-    hipError_t err = occupancy(p.dtype, p.nt, lds, p.rk, &bpc);
-    if (err != hipSuccess)
-        return hip_fail(err, "occupancy query");
-    if (bpc < 1)
-        return fail(SEM_ERR_UNSUPPORTED, "batch kernel cannot be resident with %d B of LDS", lds);
-    return SEM_OK;
-}
-
-sem_status upload_blocks(PlanCore& p, hipStream_t s)
-{
-    if (p.d_blocks)
-        (void)hipFree(p.d_blocks);
-    p.d_blocks = nullptr;
-    const size_t bt_bytes = p.blocks.size() *
-                            (p.dtype == SEM_F64 ? sizeof(semk::BatchBlock<double>)
-                                                : sizeof(semk::BatchBlock<float>));
-    hipError_t err = hipMalloc(&p.d_blocks, bt_bytes);
-    if (err != hipSuccess)
-        return fail(SEM_ERR_NO_MEMORY, "plan block table (%zu B): %s", bt_bytes,
-                    hipGetErrorString(err));
-    if (p.dtype == SEM_F64) {
-        auto hb = host_block_table<double>(p);
-        err = hipMemcpyAsync(p.d_blocks, hb.data(), bt_bytes, hipMemcpyHostToDevice, s);
-        if (err == hipSuccess)
-            err = hipStreamSynchronize(s);
-    } else {
-        auto hb = host_block_table<float>(p);
-        err = hipMemcpyAsync(p.d_blocks, hb.data(), bt_bytes, hipMemcpyHostToDevice, s);
-        if (err == hipSuccess)
-            err = hipStreamSynchronize(s);
-    }
-    if (err != hipSuccess)
-        return hip_fail(err, "upload block table");
-    return SEM_OK;
-}
-
-// Upload the tile table for the current choices and check that the chosen
-// workgroup size and LDS can be resident.
-sem_status finalize(PlanCore& p, hipStream_t s)
-{
-    SEM_TRY(upload_blocks(p, s));
-    if (p.d_tiles)
-        (void)hipFree(p.d_tiles);
-    p.d_tiles = nullptr;
-    std::vector<semh::Tile> tiles = make_tiles(p.blocks, p.orders, 0);
-    p.ntiles = (int)tiles.size();
-    p.lds_bytes = lds_for(p.dtype, p.nt, p.orders);
-    hipError_t err = hipMalloc((void**)&p.d_tiles, tiles.size() * sizeof(semh::Tile));
-    if (err != hipSuccess)
-        return fail(SEM_ERR_NO_MEMORY, "plan tile table: %s", hipGetErrorString(err));
-    err = hipMemcpyAsync(p.d_tiles, tiles.data(), tiles.size() * sizeof(semh::Tile),
-                         hipMemcpyHostToDevice, s);
-    if (err == hipSuccess)
-        err = hipStreamSynchronize(s);
-    if (err != hipSuccess)
-        return hip_fail(err, "upload tile table");
-    return check_resident(p, p.lds_bytes);
-}
-
-// ---------------------------------------------------------------------------
-// Plan cache: a flat JSON object {"key": {"epb": E, "layout": L, "us": T}} in
-// the file named by SEM_PLAN_CACHE, keyed by device arch, dtype, workgroup
-// size, the LDS cap of the launch, Nq and a power-of-two element bucket.
-// ---------------------------------------------------------------------------
-std::mutex g_cache_mu;
-
-struct CacheEntry {
-    int epb = 0;
-    int lay = 0;
-    double us = -1.0;
-};
-
-std::string cache_path()
-{
-    const char* p = getenv("SEM_PLAN_CACHE");
-    return p ? std::string(p) : std::string();
-}
-
-std::string arch_name(int device)
-{
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
-        return "unknown";
-    std::string a = prop.gcnArchName;
-    size_t c = a.find(':');
-    return c == std::string::npos ? a : a.substr(0, c);
-}
-
-std::string cache_key(const std::string& arch, sem_dtype dt, bool rk, int nt, int cap, int nq,
-                      int64_t ne)
-{
-    int64_t bucket = 1;
-    while (bucket < ne)
-        bucket <<= 1;
-    char buf[160];
-    snprintf(buf, sizeof buf, "%s/%s%s/nt%d/lds%d/nq%d/ne%lld", arch.c_str(),
-             dt == SEM_F64 ? "f64" : "f32", rk ? "-rk" : "", nt, cap, nq, (long long)bucket);
-    return buf;
-}
-
-double json_number(const std::string& body, const char* name, double dflt)
-{
-    const std::string key = std::string("\"") + name + "\"";
-    size_t k = body.find(key);
-    if (k == std::string::npos)
-        return dflt;
-    size_t c = body.find(':', k);
-    if (c == std::string::npos)
-        return dflt;
-    return atof(body.c_str() + c + 1);
-}
-
-std::map<std::string, CacheEntry> cache_read(const std::string& path)
-{
-    std::map<std::string, CacheEntry> m;
-    FILE* f = fopen(path.c_str(), "rb");
-    if (!f)
-        return m;
-    std::string s;
-    char buf[4096];
-    size_t n;
-    while ((n = fread(buf, 1, sizeof buf, f)) > 0)
-        s.append(buf, n);
-    fclose(f);
-    size_t pos = 0;
-    while (true) {
-        size_t k0 = s.find('"', pos);
-        if (k0 == std::string::npos)
-            break;
-        size_t k1 = s.find('"', k0 + 1);
-        if (k1 == std::string::npos)
-            break;
-        std::string key = s.substr(k0 + 1, k1 - k0 - 1);
-        size_t ob = s.find('{', k1);
-        size_t cb = s.find('}', k1);
-        if (ob == std::string::npos || cb == std::string::npos || cb < ob)
-            break;
-        std::string body = s.substr(ob, cb - ob);
-        CacheEntry e;
-        e.epb = (int)json_number(body, "epb", 0);
-        e.lay = (int)json_number(body, "layout", 0);
-        e.us = json_number(body, "us", -1.0);
-        if (e.epb > 0)
-            m[key] = e;
-        pos = cb + 1;
-    }
-    return m;
-}
-
-void cache_write(const std::string& path, const std::map<std::string, CacheEntry>& m)
-{
-    std::string tmp = path + ".tmp";
-    FILE* f = fopen(tmp.c_str(), "wb");
-    if (!f)
-        return;
-    fprintf(f, "{\n");
-    size_t i = 0;
-    for (const auto& kv : m)
-        fprintf(f, "  \"%s\": {\"epb\": %d, \"layout\": %d, \"us\": %.3f}%s\n", kv.first.c_str(),
-                kv.second.epb, kv.second.lay, kv.second.us, ++i < m.size() ? "," : "");
-    fprintf(f, "}\n");
-    fclose(f);
-    rename(tmp.c_str(), path.c_str());
-}
-
-// Time one order's blocks alone with the shape currently in p.orders, under
-// the dynamic LDS `cap` that the combined launch will use (it sets the
-// occupancy): median of 5 launches after 2 warm-ups, HIP events.
-sem_status time_candidate(PlanCore& p, int nq, int cap, hipStream_t s, double* us_out)
-{
-    std::vector<semh::Tile> tiles = make_tiles(p.blocks, p.orders, nq);
-    SEM_TRY(check_resident(p, cap));
-    semh::Tile* d_t = nullptr;
-    hipError_t err = hipMalloc((void**)&d_t, tiles.size() * sizeof(semh::Tile));
-    if (err != hipSuccess)
-        return fail(SEM_ERR_NO_MEMORY, "autotune tile table: %s", hipGetErrorString(err));
-    err = hipMemcpy(d_t, tiles.data(), tiles.size() * sizeof(semh::Tile), hipMemcpyHostToDevice);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (err == hipSuccess)
-        err = hipEventCreate(&e0);
-    if (err == hipSuccess)
-        err = hipEventCreate(&e1);
-    std::vector<float> ms;
-    for (int r = 0; r < 7 && err == hipSuccess; ++r) {
-        err = hipEventRecord(e0, s);
-        if (err == hipSuccess)
-            err = launch(p, d_t, (int)tiles.size(), cap, s);
-        if (err == hipSuccess)
-            err = hipEventRecord(e1, s);
-        if (err == hipSuccess)
-            err = hipEventSynchronize(e1);
-        float t = 0.f;
-        if (err == hipSuccess && r >= 2 && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
-            ms.push_back(t);
-    }
-    if (e0)
-        (void)hipEventDestroy(e0);
-    if (e1)
-        (void)hipEventDestroy(e1);
-    (void)hipFree(d_t);
-    if (err != hipSuccess)
-        return hip_fail(err, "autotune launch");
-    std::sort(ms.begin(), ms.end());
-    *us_out = ms.empty() ? 1e30 : 1e3 * ms[ms.size() / 2];
-    return SEM_OK;
-}
-
-// For every workgroup size and every LDS cap (the LDS of a compiled shape),
-// pick per order the fastest shape that fits under the cap, timed at that
-// cap; keep the (size, cap) whose per-order times sum lowest.  The launch's
-// occupancy is set by its largest shape, so timing each order at the cap it
-// will share is what makes the per-order choices add up.
-sem_status autotune(PlanCore& p, bool use_cache, hipStream_t s)
-{
-    const std::string arch = arch_name(p.device);
-    const std::string path = use_cache ? cache_path() : std::string();
-    std::map<std::string, CacheEntry> cache;
-    if (!path.empty()) {
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        cache = cache_read(path);
-    }
-    SEM_TRY(upload_blocks(p, s));
-    bool all_cached = true;
-    double best_total = 1e300;
-    int best_nt = 0, best_cap = 0;
-    std::vector<OrderChoice> best_orders;
-    for (int nt : semh::kBatchThreads) {
-        p.nt = nt;
-        std::vector<int> caps;
-        for (int i = 0; i < semh::kNumVariants; ++i) {
-            const semh::VariantDef v = semh::kVariants[i];
-            bool used = false;
-            for (const OrderChoice& o : p.orders)
-                used |= o.nq == v.nq;
-            if (used && variant_ok(p.dtype, nt, v.nq, v.epb, v.lay, p.rk))
-                caps.push_back(shape_lds(p.dtype, nt, v.nq, v.epb, v.lay));
-        }
-        std::sort(caps.begin(), caps.end());
-        caps.erase(std::unique(caps.begin(), caps.end()), caps.end());
-        for (int cap : caps) {
-            std::vector<OrderChoice> chosen = p.orders;
-            double total = 0.0;
-            bool feasible = true;
-            for (OrderChoice& oc : chosen) {
-                const std::string key = cache_key(arch, p.dtype, p.rk, nt, cap, oc.nq, oc.elements);
-                auto it = cache.find(key);
-                if (it != cache.end() &&
-                    variant_ok(p.dtype, nt, oc.nq, it->second.epb, it->second.lay, p.rk) &&
-                    shape_lds(p.dtype, nt, oc.nq, it->second.epb, it->second.lay) <= cap) {
-                    oc.epb = it->second.epb;
-                    oc.lay = it->second.lay;
-                    oc.us = it->second.us;
-                    total += oc.us;
-                    continue;
-                }
-                double best = 1e300;
-                int best_epb = -1, best_lay = 0;
-                for (int i = 0; i < semh::kNumVariants; ++i) {
-                    const semh::VariantDef v = semh::kVariants[i];
-                    if (v.nq != oc.nq || !variant_ok(p.dtype, nt, v.nq, v.epb, v.lay, p.rk) ||
-                        shape_lds(p.dtype, nt, v.nq, v.epb, v.lay) > cap)
-                        continue;
-                    all_cached = false;
-                    for (OrderChoice& o : p.orders)
-                        if (o.nq == oc.nq) {
-                            o.epb = v.epb;
-                            o.lay = v.lay;
-                        }
-                    double us = 0.0;
-                    SEM_TRY(time_candidate(p, oc.nq, cap, s, &us));
-                    if (log_enabled())
-                        fprintf(stderr, "[semvol] autotune %s nt=%d lds<=%d nq=%d epb=%d layout=%d: %.2f us\n",
-                                p.dtype == SEM_F64 ? "f64" : "f32", nt, cap, v.nq, v.epb, v.lay, us);
-                    if (us < best) {
-                        best = us;
-                        best_epb = v.epb;
-                        best_lay = v.lay;
-                    }
-                }
-                if (best_epb < 0) {
-                    feasible = false;
-                    break;
-                }
-                oc.epb = best_epb;
-                oc.lay = best_lay;
-                oc.us = best;
-                total += best;
-                cache[key] = CacheEntry{best_epb, best_lay, best};
-            }
-            if (feasible && total < best_total) {
-                best_total = total;
-                best_nt = nt;
-                best_cap = cap;
-                best_orders = chosen;
-            }
-        }
-    }
-    if (best_orders.empty())
-        return fail(SEM_ERR_UNSUPPORTED, "no batch tile shape fits every order of the plan");
-    p.nt = best_nt;
-    p.orders = best_orders;
-    p.autotuned = true;
-    p.from_cache = all_cached;
-    if (!path.empty() && !all_cached) {
-        std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto merged = cache_read(path);
-        for (auto& kv : cache)
-            merged[kv.first] = kv.second;
-        cache_write(path, merged);
-    }
-    if (log_enabled())
-        fprintf(stderr, "[semvol] autotune chose nt=%d, LDS cap %d B (sum of per-order times %.2f us)%s\n",
-                p.nt, best_cap, best_total, all_cached ? " from cache" : "");
-    return SEM_OK;
-}
-
-// Built-in batch shapes (no autotuning): the smallest workgroup size among
-// 256, 512 and 1024 for which every order has its single-order default tile
-// (all fluxes in LDS, else one direction at a time).
-sem_status default_shapes(PlanCore& p)
-{
-    for (int nt : semh::kBatchThreads) {
-        bool all = true;
-        for (OrderChoice& o : p.orders) {
-            // the single-order default shape, else the historical small
-            // shapes with all fluxes resident, else aliased
-            const DefaultTile dft = default_tile(p.dtype, o.nq);
-            o.epb = dft.epb;
-            o.lay = dft.lay;
-            if (variant_ok(p.dtype, nt, o.nq, o.epb, o.lay, p.rk))
-                continue;
-            o.epb = default_epb(o.nq);
-            if (variant_ok(p.dtype, nt, o.nq, o.epb, semk::FULL, p.rk))
-                o.lay = semk::FULL;
-            else if (variant_ok(p.dtype, nt, o.nq, o.epb, semk::ALIAS, p.rk))
-                o.lay = semk::ALIAS;
-            else
-                all = false;
-        }
-        if (all) {
-            p.nt = nt;
-            return SEM_OK;
-        }
-    }
-    return fail(SEM_ERR_UNSUPPORTED, "no default batch shape covers every order of the plan");
-}
-
-sem_status build_plan(const sem_block* blocks, int32_t nblocks, sem_dtype dt, const sem_phys* phys,
-                      uint32_t flags, hipStream_t s, const PlanCore* template_plan,
-                      const semk::RkStage* rk, const void* const* rk_x, PlanCore** out)
-{
-    SEM_TRY(check_dtype(dt));
-    if (!out)
-        return fail(SEM_ERR_INVALID_ARG, "out is NULL");
-    *out = nullptr;
-    if (!blocks || nblocks < 1)
-        return fail(SEM_ERR_INVALID_ARG, "need at least one block (nblocks = %d)", nblocks);
-    if (!phys)
-        return fail(SEM_ERR_INVALID_ARG, "phys is NULL");
-    for (int i = 0; i < nblocks; ++i)
-        SEM_TRY(check_block(blocks[i], i, dt, phys));
-    PlanCore* p = new (std::nothrow) PlanCore();
-    if (!p)
-        return fail(SEM_ERR_NO_MEMORY, "plan allocation");
-    p->dtype = dt;
-    p->phys = to_phys(phys);
-    p->blocks.assign(blocks, blocks + nblocks);
-    if (rk) {
-        p->rk = true;
-        p->rk_stage = *rk;
-        p->rk_x.assign(rk_x, rk_x + nblocks);
-    }
-    hipError_t err = hipGetDevice(&p->device);
-    if (err == hipSuccess)
-        err = dt == SEM_F64 ? semh::batch_prepare<double>() : semh::batch_prepare<float>();
-    if (err != hipSuccess) {
-        delete p;
-        return hip_fail(err, "batch kernel setup");
-    }
-    for (int i = 0; i < nblocks; ++i) {
-        bool found = false;
-        for (OrderChoice& o : p->orders)
-            if (o.nq == blocks[i].Nq) {
-                o.elements += blocks[i].Ne;
-                found = true;
-            }
-        if (!found) {
-            OrderChoice o;
-            o.nq = blocks[i].Nq;
-            o.elements = blocks[i].Ne;
-            p->orders.push_back(o);
-        }
-    }
-    std::sort(p->orders.begin(), p->orders.end(),
-              [](const OrderChoice& a, const OrderChoice& b) { return a.nq < b.nq; });
-    sem_status st = SEM_OK;
-    if (template_plan) {
-        p->nt = template_plan->nt;
-        p->orders = template_plan->orders;
-        p->autotuned = template_plan->autotuned;
-        p->from_cache = template_plan->from_cache;
-    } else if (flags & SEM_PLAN_AUTOTUNE) {
-        st = autotune(*p, (flags & SEM_PLAN_USE_CACHE) != 0, s);
-    } else {
-        st = default_shapes(*p);
-    }
-    if (st == SEM_OK)
-        st = finalize(*p, s);
-    if (st != SEM_OK) {
-        free_core(p);
-        delete p;
-        return st;
-    }
-    *out = p;
-    return SEM_OK;
-}
-
-}  // namespace
-
-struct sem_plan_s {
-    PlanCore core;
-};
-
-extern "C" sem_status sem_batch_plan(const sem_block* blocks, int32_t nblocks, sem_dtype dtype,
-                                     const sem_phys* phys, uint32_t flags, void* stream,
-                                     sem_plan* out)
-{
-    if (!out)
-        return fail(SEM_ERR_INVALID_ARG, "out is NULL");
-    *out = nullptr;
-    PlanCore* core = nullptr;
-    SEM_TRY(build_plan(blocks, nblocks, dtype, phys, flags, static_cast<hipStream_t>(stream), nullptr,
-                       nullptr, nullptr, &core));
-    sem_plan p = new (std::nothrow) sem_plan_s();
-    if (!p) {
-        free_core(core);
-        delete core;
-        return fail(SEM_ERR_NO_MEMORY, "plan allocation");
-    }
-    p->core = *core;   // takes over the device tables
-    delete core;
-    *out = p;
-    return SEM_OK;
-}
-
-extern "C" sem_status sem_batch_execute(sem_plan plan, void* stream)
-{
-    if (!plan)
-        return fail(SEM_ERR_INVALID_ARG, "plan is NULL");
-    const PlanCore& c = plan->core;
-    if (!c.d_tiles || !c.d_blocks)
-        return fail(SEM_ERR_INVALID_ARG, "plan has no device tables (destroyed?)");
-    hipError_t err = launch(c, c.d_tiles, c.ntiles, c.lds_bytes, static_cast<hipStream_t>(stream));
-    if (err != hipSuccess)
-        return hip_fail(err, "batch kernel launch");
-    return SEM_OK;
-}
-
-namespace {
-std::string describe(const PlanCore& c)
-{
-    std::string s = "{\"dtype\": \"";
-    s += c.dtype == SEM_F64 ? "f64" : "f32";
-    char tmp[256];
-    snprintf(tmp, sizeof tmp,
-             "\", \"threads\": %d, \"lds_bytes\": %d, \"tiles\": %d, "
-             "\"blocks\": %zu, \"fused_rk_stage\": %s, \"autotuned\": %s, \"from_cache\": %s, "
-             "\"orders\": [",
-             c.nt, c.lds_bytes, c.ntiles, c.blocks.size(), c.rk ? "true" : "false",
-             c.autotuned ? "true" : "false", c.from_cache ? "true" : "false");
-    s += tmp;
-    for (size_t i = 0; i < c.orders.size(); ++i) {
-        snprintf(tmp, sizeof tmp,
-                 "%s{\"Nq\": %d, \"elems_per_block\": %d, \"layout\": \"%s\", \"elements\": %lld, "
-                 "\"tuned_us\": %.3f}",
-                 i ? ", " : "", c.orders[i].nq, c.orders[i].epb,
-                 c.orders[i].lay == semk::ALIAS ? "alias" : "full", (long long)c.orders[i].elements,
-                 c.orders[i].us);
-        s += tmp;
-    }
-    s += "]}";
-    return s;
-}
-}  // namespace
-
-extern "C" sem_status sem_plan_describe(sem_plan plan, char* buf, int32_t len)
-{
-    if (!plan || !buf || len < 1)
-        return fail(SEM_ERR_INVALID_ARG, "NULL plan or buffer");
-    snprintf(buf, (size_t)len, "%s", describe(plan->core).c_str());
-    return SEM_OK;
-}
-
-extern "C" sem_status sem_plan_destroy(sem_plan plan)
-{
-    if (!plan)
-        return fail(SEM_ERR_INVALID_ARG, "plan is NULL");
-    free_core(&plan->core);
-    delete plan;
-    return SEM_OK;
-}
-
-// ===========================================================================
-// SSP-RK3 step in a HIP graph
-// ===========================================================================
-struct sem_rk3_s {
-    PlanCore stage[3];
-    bool fused = true;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-};
-
-extern "C" sem_status sem_rk3_graph_create(const sem_block* blocks, int32_t nblocks, sem_dtype dtype,
-                                           const sem_phys* phys, uint32_t flags, void* q_n,
-                                           void* q_1, void* q_2, void* L, int64_t n, double dt,
-                                           void* stream, sem_rk3* out)
-{
-    if (!out)
-        return fail(SEM_ERR_INVALID_ARG, "out is NULL");
-    *out = nullptr;
-    SEM_TRY(check_dtype(dtype));
-    const size_t es = elem_size(dtype);
-    SEM_TRY(check_ptr(q_n, es, "q_n"));
-    SEM_TRY(check_ptr(q_1, es, "q_1"));
-    SEM_TRY(check_ptr(q_2, es, "q_2"));
-    SEM_TRY(check_ptr(L, es, "L"));
-    if (n < 1)
-        return fail(SEM_ERR_INVALID_ARG, "n = %lld < 1", (long long)n);
-    if (!blocks || nblocks < 1)
-        return fail(SEM_ERR_INVALID_ARG, "need at least one block");
-    if (!std::isfinite(dt))
-        return fail(SEM_ERR_INVALID_ARG, "dt is not finite");
-    const bool fused = (flags & SEM_RK3_SEPARATE_STAGES) == 0;
-    // Shu-Osher coefficients: stage k writes a_k q_n + b_k (q_k + dt v(q_k))
-    const double a[3] = {0.0, 0.75, 1.0 / 3.0};
-    const double b[3] = {1.0, 0.25, 2.0 / 3.0};
-    char* qin[3] = {static_cast<char*>(q_n), static_cast<char*>(q_1), static_cast<char*>(q_2)};
-    char* qout[3] = {static_cast<char*>(q_1), static_cast<char*>(q_2), static_cast<char*>(q_n)};
-    // every block's q inside q_n and its rhs inside L at the same offset
-    std::vector<sem_block> sb[3];
-    std::vector<const void*> xs(nblocks);
-    const char* qn = static_cast<const char*>(q_n);
-    const char* lb = static_cast<const char*>(L);
-    for (int k = 0; k < 3; ++k)
-        sb[k].assign(blocks, blocks + nblocks);
-    for (int i = 0; i < nblocks; ++i) {
-        const int64_t m = (int64_t)blocks[i].Nq * blocks[i].Nq * blocks[i].Nq;
-        const int64_t bytes = (int64_t)blocks[i].Ne * 5 * m * (int64_t)es;
-        const int64_t off = static_cast<const char*>(blocks[i].q) - qn;
-        const int64_t roff = static_cast<const char*>((const void*)blocks[i].rhs) - lb;
-        if (off < 0 || off + bytes > n * (int64_t)es)
-            return fail(SEM_ERR_INVALID_ARG, "block %d: q is not inside q_n[0, n)", i);
-        if (roff != off)
-            return fail(SEM_ERR_INVALID_ARG, "block %d: rhs is not at the same offset in L as q in q_n",
-                        i);
-        xs[i] = qn + off;
-        for (int k = 0; k < 3; ++k) {
-            sb[k][i].q = qin[k] + off;
-            if (fused)
-                sb[k][i].rhs = qout[k] + off;   // the fused stage writes q_{k+1} directly
-        }
-    }
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    sem_rk3 g = new (std::nothrow) sem_rk3_s();
-    if (!g)
-        return fail(SEM_ERR_NO_MEMORY, "graph allocation");
-    g->fused = fused;
-    PlanCore* c[3] = {nullptr, nullptr, nullptr};
-    sem_status st = SEM_OK;
-    for (int k = 0; k < 3 && st == SEM_OK; ++k) {
-        const semk::RkStage rk{a[k], b[k], dt};
-        st = build_plan(sb[k].data(), nblocks, dtype, phys, k == 0 ? flags : 0, s,
-                        k == 0 ? nullptr : c[0], fused ? &rk : nullptr, fused ? xs.data() : nullptr,
-                        &c[k]);
-    }
-    if (st != SEM_OK) {
-        for (PlanCore* ck : c)
-            if (ck) {
-                free_core(ck);
-                delete ck;
-            }
-        delete g;
-        return st;
-    }
-    for (int k = 0; k < 3; ++k) {
-        g->stage[k] = *c[k];
-        delete c[k];
-    }
-    auto destroy_all = [&]() {
-        for (PlanCore& ck : g->stage)
-            free_core(&ck);
-        if (g->exec)
-            (void)hipGraphExecDestroy(g->exec);
-        if (g->graph)
-            (void)hipGraphDestroy(g->graph);
-        delete g;
-    };
-    hipStream_t cs = nullptr;
-    hipError_t err = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (err != hipSuccess) {
-        destroy_all();
-        return hip_fail(err, "capture stream");
-    }
-    err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    for (int k = 0; k < 3 && err == hipSuccess; ++k) {
-        const PlanCore& ck = g->stage[k];
-        err = launch(ck, ck.d_tiles, ck.ntiles, ck.lds_bytes, cs);
-        if (err == hipSuccess && !fused) {
-            if (dtype == SEM_F64)
-                err = semh::launch_axpby<double>(n, a[k], static_cast<const double*>(q_n), b[k],
-                                                 reinterpret_cast<const double*>(qin[k]), dt,
-                                                 static_cast<const double*>(L),
-                                                 reinterpret_cast<double*>(qout[k]), cs);
-            else
-                err = semh::launch_axpby<float>(n, a[k], static_cast<const float*>(q_n), b[k],
-                                                reinterpret_cast<const float*>(qin[k]), dt,
-                                                static_cast<const float*>(L),
-                                                reinterpret_cast<float*>(qout[k]), cs);
-        }
-    }
-    hipGraph_t graph = nullptr;
-    hipError_t err_end = hipStreamEndCapture(cs, &graph);
-    if (err == hipSuccess)
-        err = err_end;
-    g->graph = graph;
-    if (err == hipSuccess)
-        err = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
-    (void)hipStreamDestroy(cs);
-    if (err != hipSuccess) {
-        destroy_all();
-        return hip_fail(err, "RK3 graph capture");
-    }
-    *out = g;
-    return SEM_OK;
-}
-
-extern "C" sem_status sem_rk3_graph_launch(sem_rk3 step, void* stream)
-{
-    if (!step || !step->exec)
-        return fail(SEM_ERR_INVALID_ARG, "step is NULL or destroyed");
-    hipError_t err = hipGraphLaunch(step->exec, static_cast<hipStream_t>(stream));
-    if (err != hipSuccess)
-        return hip_fail(err, "hipGraphLaunch");
-    return SEM_OK;
-}
-
-extern "C" sem_status sem_rk3_graph_describe(sem_rk3 step, char* buf, int32_t len)
-{
-    if (!step || !buf || len < 1)
-        return fail(SEM_ERR_INVALID_ARG, "NULL step or buffer");
-    std::string s = std::string("{\"fused_stages\": ") + (step->fused ? "true" : "false") +
-                    ", \"stage_plan\": " + describe(step->stage[0]) + "}";
-    snprintf(buf, (size_t)len, "%s", s.c_str());
-    return SEM_OK;
-}
-
-extern "C" sem_status sem_rk3_graph_destroy(sem_rk3 step)
-{
-    if (!step)
-        return fail(SEM_ERR_INVALID_ARG, "step is NULL");
-    for (PlanCore& c : step->stage)
-        free_core(&c);
-    if (step->exec)
-        (void)hipGraphExecDestroy(step->exec);
-    if (step->graph)
-        (void)hipGraphDestroy(step->graph);
-    delete step;
-    return SEM_OK;
-}
