@@ -20,8 +20,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <type_traits>
-
 namespace semk {
 
 struct Phys {
@@ -155,17 +153,7 @@ struct Shape {
 // a time and walks the directions in separate LDS phases, trading barriers
 // for a fraction of the LDS, which lets large elements (Nq >= 9) and the
 // worst-case shape of a mixed-order batch keep more workgroups resident.
-// ALIAS2 (extended kernels only) stages one direction and half of the fields
-// at a time, for elements whose aliased stage alone would leave less than
-// two workgroups per CU.
-enum Layout : int { FULL = 0, ALIAS = 1, ALIAS2 = 2 };
-
-// Fields staged per LDS pass of a layout.
-template <int LAY, int NF>
-constexpr int fields_per_pass()
-{
-    return LAY == ALIAS2 ? (NF + 1) / 2 : NF;
-}
+enum Layout : int { FULL = 0, ALIAS = 1 };
 
 // Fields per node: NF = 5 (rho, U1, U2, U3, Theta) or 8 (plus the passive
 // tracers Q1..Q3, whose flux is U_a Q_i / rho).  Active reference directions:
@@ -207,8 +195,8 @@ constexpr int alias_max_nodes_per_thread()
 template <typename T, int NQ, int EPB, int NT, int LAY, int NF = 5, int DIRS = 7>
 constexpr int volume_tile_values_per_node()
 {
-    if (LAY != FULL)
-        return fields_per_pass<LAY, NF>();
+    if (LAY == ALIAS)
+        return NF;
     return ndirs<DIRS>() * NF + (nodes_per_thread<NQ, EPB, NT>() > 1 ? 2 : 0);
 }
 
@@ -340,30 +328,24 @@ __device__ __forceinline__ void load_node(const BlockPtrs<T>& B, const Phys& ph,
 
 // Contravariant flux of direction d (sum_a g_ad f_a) of one node into LDS:
 // F[b*M] for the fields b = rho, U1, U2, U3, Theta (and the tracers).
-// Fields [B0, B1) only (F then points at field B0) when a tile stages the
-// fields in groups.
-template <typename T, int M, int NF, int B0 = 0, int B1 = NF>
+template <typename T, int M, int NF>
 __device__ __forceinline__ void put_flux(const NodeState<T, NF>& st, int d, T* __restrict__ F)
 {
     const T g1 = st.g[3 * d], g2 = st.g[3 * d + 1], g3 = st.g[3 * d + 2];
     const T Ud = g1 * st.U1 + g2 * st.U2 + g3 * st.U3;   // contravariant momentum
     const T vd = Ud * st.rinv;
-    T f[NF];
-    f[0] = Ud;
-    f[1] = st.U1 * vd + g1 * st.pp;
-    f[2] = st.U2 * vd + g2 * st.pp;
-    f[3] = st.U3 * vd + g3 * st.pp;
-    f[4] = st.Th * vd;
+    F[0] = Ud;
+    F[M] = st.U1 * vd + g1 * st.pp;
+    F[2 * M] = st.U2 * vd + g2 * st.pp;
+    F[3 * M] = st.U3 * vd + g3 * st.pp;
+    F[4 * M] = st.Th * vd;
 #pragma unroll
     for (int b = 5; b < NF; ++b)
-        f[b] = st.Q[b - 5] * vd;
-#pragma unroll
-    for (int b = B0; b < B1; ++b)
-        F[(b - B0) * M] = f[b];
+        F[b * M] = st.Q[b - 5] * vd;
 }
 
 // acc[b] += sum_n D[row][n] F_b(base + n*stride), b < NF, out of LDS.
-template <typename T, int NQ, int M, int NF, int B0 = 0, int B1 = NF>
+template <typename T, int NQ, int M, int NF>
 __device__ __forceinline__ void contract(const T* __restrict__ sD, const T* __restrict__ F, int row,
                                          int stride, T (&acc)[NF])
 {
@@ -371,24 +353,24 @@ __device__ __forceinline__ void contract(const T* __restrict__ sD, const T* __re
     for (int n = 0; n < NQ; ++n) {
         const T dn = sD[row * NQ + n];
 #pragma unroll
-        for (int b = B0; b < B1; ++b)
-            acc[b] += dn * F[(b - B0) * M + n * stride];
+        for (int b = 0; b < NF; ++b)
+            acc[b] += dn * F[b * M + n * stride];
     }
 }
 
 // D along direction d for the node (i, j, k): r runs over i (stride 1),
 // s over j (stride Nq), t over k (stride Nq^2).
-template <typename T, int NQ, int M, int NF, int B0 = 0, int B1 = NF>
+template <typename T, int NQ, int M, int NF>
 __device__ __forceinline__ void contract_dir(const T* __restrict__ sD, const T* __restrict__ Fd,
                                              int d, int i, int j, int k, T (&acc)[NF])
 {
     constexpr int NQ2 = NQ * NQ;
     if (d == 0)
-        contract<T, NQ, M, NF, B0, B1>(sD, Fd + NQ * j + NQ2 * k, i, 1, acc);
+        contract<T, NQ, M, NF>(sD, Fd + NQ * j + NQ2 * k, i, 1, acc);
     else if (d == 1)
-        contract<T, NQ, M, NF, B0, B1>(sD, Fd + i + NQ2 * k, j, NQ, acc);
+        contract<T, NQ, M, NF>(sD, Fd + i + NQ2 * k, j, NQ, acc);
     else
-        contract<T, NQ, M, NF, B0, B1>(sD, Fd + i + NQ * j, k, NQ2, acc);
+        contract<T, NQ, M, NF>(sD, Fd + i + NQ * j, k, NQ2, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -481,9 +463,7 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
     }
 }
 
-// FG: fields staged per LDS pass (NF, or half of them for ALIAS2 tiles).
-template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK, int NF, int DIRS, bool GEOE,
-          int FG = NF>
+template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK, int NF, int DIRS, bool GEOE>
 __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t e0, int ne,
                                                   const Phys& ph, const RkStage& rk,
                                                   T* __restrict__ smem)
@@ -494,7 +474,6 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
     constexpr int NPT = nodes_per_thread<NQ, EPB, NT>();
     static_assert(NPT <= alias_max_nodes_per_thread<T>(),
                   "ALIAS tiles keep every node's state of a thread in registers");
-    static_assert(FG >= (NF + 1) / 2 && FG <= NF, "at most two field groups");
     T* __restrict__ sD = smem;
     T* __restrict__ sF = smem + Shape<NQ>::template d_slots<T>();
     const int tid = threadIdx.x;
@@ -519,17 +498,18 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
             rn[p].load(B, rk, e0 + es, t - es * M, M, st[p]);
         }
     }
-    // one LDS pass: direction d, fields [B0, B1)
-    auto pass = [&](int d, auto b0, auto b1, bool first) {
-        constexpr int B0 = decltype(b0)::value, B1 = decltype(b1)::value;
-        if (!first)
-            __syncthreads();   // every read of the previous pass is done
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        if (!((DIRS >> d) & 1))
+            continue;
+        if (dir_slot<DIRS>(d) > 0)
+            __syncthreads();   // every read of the previous direction is done
 #pragma unroll
         for (int p = 0; p < NPT; ++p)
             if (live[p]) {
                 const int t = tid + p * NT;
                 const int es = t / M;
-                put_flux<T, M, NF, B0, B1>(st[p], d, sF + es * (FG * M) + (t - es * M));
+                put_flux<T, M, NF>(st[p], d, sF + es * (NF * M) + (t - es * M));
             }
         __syncthreads();
 #pragma unroll
@@ -538,18 +518,9 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
                 const int t = tid + p * NT;
                 const int es = t / M;
                 const int m = t - es * M;
-                contract_dir<T, NQ, M, NF, B0, B1>(sD, sF + es * (FG * M), d, m % NQ,
-                                                   (m / NQ) % NQ, m / NQ2, acc[p]);
+                contract_dir<T, NQ, M, NF>(sD, sF + es * (NF * M), d, m % NQ, (m / NQ) % NQ,
+                                           m / NQ2, acc[p]);
             }
-    };
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        if (!((DIRS >> d) & 1))
-            continue;
-        pass(d, std::integral_constant<int, 0>{}, std::integral_constant<int, FG>{},
-             dir_slot<DIRS>(d) == 0);
-        if constexpr (FG < NF)
-            pass(d, std::integral_constant<int, FG>{}, std::integral_constant<int, NF>{}, false);
     }
 #pragma unroll
     for (int p = 0; p < NPT; ++p)
@@ -568,9 +539,6 @@ __device__ __forceinline__ void volume_tile(const BlockPtrs<T>& B, int64_t e0, i
 {
     if constexpr (LAY == ALIAS)
         volume_tile_alias<T, NQ, EPB, NT, ACC, RK, NF, DIRS, GEOE>(B, e0, ne, ph, rk, smem);
-    else if constexpr (LAY == ALIAS2)
-        volume_tile_alias<T, NQ, EPB, NT, ACC, RK, NF, DIRS, GEOE, fields_per_pass<ALIAS2, NF>()>(
-            B, e0, ne, ph, rk, smem);
     else
         volume_tile_full<T, NQ, EPB, NT, ACC, RK, NF, DIRS, GEOE>(B, e0, ne, ph, rk, smem);
 }
