@@ -411,7 +411,8 @@ def main(argv=None):
     r64, r32 = results["f64"], results["f32"]
     traffic = measured_traffic("volume_f64_n7")
     line = {
-        "metric": "volume-RHS elements/s at N=7 (FP64; FP32 beside it), error vs FP64 oracle",
+        # value: FP64 elements/s; GFLOP/s, the FP32 form and both errors beside it
+        "metric": "volume-RHS elements/s and GFLOP/s at N=7, FP32 vs FP64 at stated error",
         "value": r64["el_s"],
         "unit": "elements/s",
         "n_gpus": 1,
