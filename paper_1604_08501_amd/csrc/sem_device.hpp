@@ -345,11 +345,13 @@ __device__ __forceinline__ void put_flux(const NodeState<T, NF>& st, int d, T* _
 }
 
 // acc[b] += sum_n D[row][n] F_b(base + n*stride), b < NF, out of LDS.
-template <typename T, int NQ, int M, int NF>
+// UNR: unroll factor of the n loop (2 by default: full unrolling hoists every
+// LDS load and spills in tiles holding several nodes per thread).
+template <typename T, int NQ, int M, int NF, int UNR = 2>
 __device__ __forceinline__ void contract(const T* __restrict__ sD, const T* __restrict__ F, int row,
                                          int stride, T (&acc)[NF])
 {
-#pragma unroll 2
+#pragma unroll UNR
     for (int n = 0; n < NQ; ++n) {
         const T dn = sD[row * NQ + n];
 #pragma unroll
@@ -360,23 +362,24 @@ __device__ __forceinline__ void contract(const T* __restrict__ sD, const T* __re
 
 // D along direction d for the node (i, j, k): r runs over i (stride 1),
 // s over j (stride Nq), t over k (stride Nq^2).
-template <typename T, int NQ, int M, int NF>
+template <typename T, int NQ, int M, int NF, int UNR = 2>
 __device__ __forceinline__ void contract_dir(const T* __restrict__ sD, const T* __restrict__ Fd,
                                              int d, int i, int j, int k, T (&acc)[NF])
 {
     constexpr int NQ2 = NQ * NQ;
     if (d == 0)
-        contract<T, NQ, M, NF>(sD, Fd + NQ * j + NQ2 * k, i, 1, acc);
+        contract<T, NQ, M, NF, UNR>(sD, Fd + NQ * j + NQ2 * k, i, 1, acc);
     else if (d == 1)
-        contract<T, NQ, M, NF>(sD, Fd + i + NQ2 * k, j, NQ, acc);
+        contract<T, NQ, M, NF, UNR>(sD, Fd + i + NQ2 * k, j, NQ, acc);
     else
-        contract<T, NQ, M, NF>(sD, Fd + i + NQ * j, k, NQ2, acc);
+        contract<T, NQ, M, NF, UNR>(sD, Fd + i + NQ * j, k, NQ2, acc);
 }
 
 // ---------------------------------------------------------------------------
 // Forward tile: EPB elements starting at e0, of which the first ne exist.
 // ---------------------------------------------------------------------------
-template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK, int NF, int DIRS, bool GEOE>
+template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK, int NF, int DIRS, bool GEOE,
+          int UNR = 2>
 __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t e0, int ne,
                                                  const Phys& ph, const RkStage& rk,
                                                  T* __restrict__ smem)
@@ -427,7 +430,8 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
 #pragma unroll
         for (int d = 0; d < 3; ++d)
             if ((DIRS >> d) & 1)
-                contract_dir<T, NQ, M, NF>(sD, Fe + dir_slot<DIRS>(d) * (NF * M), d, i, j, k, acc);
+                contract_dir<T, NQ, M, NF, UNR>(sD, Fe + dir_slot<DIRS>(d) * (NF * M), d, i, j, k,
+                                                acc);
         store_node<T, M, NF, ACC, RK>(B, rk, e0 + es, m, acc, jinv, src, rn);
     };
 
@@ -463,7 +467,8 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
     }
 }
 
-template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK, int NF, int DIRS, bool GEOE>
+template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK, int NF, int DIRS, bool GEOE,
+          int UNR = 2>
 __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t e0, int ne,
                                                   const Phys& ph, const RkStage& rk,
                                                   T* __restrict__ smem)
@@ -518,8 +523,8 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
                 const int t = tid + p * NT;
                 const int es = t / M;
                 const int m = t - es * M;
-                contract_dir<T, NQ, M, NF>(sD, sF + es * (NF * M), d, m % NQ, (m / NQ) % NQ,
-                                           m / NQ2, acc[p]);
+                contract_dir<T, NQ, M, NF, UNR>(sD, sF + es * (NF * M), d, m % NQ, (m / NQ) % NQ,
+                                                m / NQ2, acc[p]);
             }
     }
 #pragma unroll
@@ -533,14 +538,14 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
 }
 
 template <typename T, int NQ, int EPB, int NT, int LAY, bool ACC, bool RK, int NF = 5, int DIRS = 7,
-          bool GEOE = false>
+          bool GEOE = false, int UNR = 2>
 __device__ __forceinline__ void volume_tile(const BlockPtrs<T>& B, int64_t e0, int ne,
                                             const Phys& ph, const RkStage& rk, T* __restrict__ smem)
 {
     if constexpr (LAY == ALIAS)
-        volume_tile_alias<T, NQ, EPB, NT, ACC, RK, NF, DIRS, GEOE>(B, e0, ne, ph, rk, smem);
+        volume_tile_alias<T, NQ, EPB, NT, ACC, RK, NF, DIRS, GEOE, UNR>(B, e0, ne, ph, rk, smem);
     else
-        volume_tile_full<T, NQ, EPB, NT, ACC, RK, NF, DIRS, GEOE>(B, e0, ne, ph, rk, smem);
+        volume_tile_full<T, NQ, EPB, NT, ACC, RK, NF, DIRS, GEOE, UNR>(B, e0, ne, ph, rk, smem);
 }
 
 // ---------------------------------------------------------------------------
