@@ -208,3 +208,24 @@ def test_ladder_validation(L, sv):
     assert lad(rhs=3 * A) == sv.SEM_ERR_INVALID_ARG
     assert L.sem_volume_rhs_ladder(1, 4, 8, A, 2 * A, 3 * A, None, 4 * A, None) == \
         sv.SEM_ERR_INVALID_ARG
+
+
+def test_last_error_is_per_thread(L, sv):
+    """Each thread reads the message of its own last failure."""
+    import threading
+    ph = sv.sem_phys(1e5, 1.4, 287.0, 9.81)
+    A = 1 << 20
+    seen = {}
+    barrier = threading.Barrier(2)
+
+    def worker(name, Ne, Nq):
+        st = L.sem_volume_rhs(Ne, Nq, 0, A, 2 * A, 3 * A, None, None, ctypes.byref(ph), 4 * A, 0,
+                              None)
+        barrier.wait()          # both threads have failed before either reads
+        seen[name] = (st, L.sem_last_error().decode())
+
+    t1 = threading.Thread(target=worker, args=("a", 0, 8))
+    t2 = threading.Thread(target=worker, args=("b", 4, 11))
+    t1.start(); t2.start(); t1.join(); t2.join()
+    assert seen["a"][0] == sv.SEM_ERR_INVALID_ARG and "Ne = 0" in seen["a"][1]
+    assert seen["b"][0] == sv.SEM_ERR_UNSUPPORTED and "Nq = 11" in seen["b"][1]

@@ -597,3 +597,36 @@ def test_indices_beyond_2_31(sv, oracle_mod):
         assert err(got, ref).max() <= TOL32, lo
     del q, geo, rr, tr, out
     torch.cuda.empty_cache()
+
+
+def test_concurrent_host_threads_and_streams(sv, oracle_mod):
+    """Four host threads launch on four streams at once, each with its own
+    inputs and order; every result equals the oracle's."""
+    import threading
+    cases = [I.warped_workload(N=n, n_elements=60, k=180 + n) for n in (3, 4, 6, 7)]
+    refs = [oracle_fwd(oracle_mod, w) for w in cases]
+    outs = [None] * len(cases)
+    errors = []
+
+    def worker(idx):
+        try:
+            w = cases[idx]
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                args = (dev(w.q), dev(w.geo), dev(w.D), dev(w.rho_ref), dev(w.theta_ref))
+                out = None
+                for _ in range(20):
+                    out = sv.volume_rhs(*args, w.phys.as_tuple(), out=out)
+            s.synchronize()
+            outs[idx] = out.cpu().numpy()
+        except Exception as ex:       # reported below, in the main thread
+            errors.append(ex)
+
+    threads = [threading.Thread(target=worker, args=(i,)) for i in range(len(cases))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    for w, got, ref in zip(cases, outs, refs):
+        assert err(got, ref).max() <= TOL64, w.N
