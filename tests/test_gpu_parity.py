@@ -630,3 +630,45 @@ def test_concurrent_host_threads_and_streams(sv, oracle_mod):
     assert not errors, errors
     for w, got, ref in zip(cases, outs, refs):
         assert err(got, ref).max() <= TOL64, w.N
+
+
+def test_calls_inside_a_captured_graph(sv):
+    """sem_volume_rhs, sem_volume_rhs_adjoint and a batch plan's launch record
+    into a graph captured by the caller (they allocate nothing and record no
+    memset); every replay, with eager work between replays, equals the eager
+    result."""
+    w = I.warped_workload(N=5, n_elements=200, k=190)
+    phys = w.phys.as_tuple()
+    q, geo, D, rr, tr, lam = (dev(a) for a in (w.q, w.geo, w.D, w.rho_ref, w.theta_ref,
+                                               np.random.default_rng(3).standard_normal(w.q.shape)))
+    ws = I.mixed_order_workloads(orders=(3, 6), per_order=50, k=191)
+    blocks = _batch(ws, torch.float64)
+    plan = sv.BatchPlan(blocks, ws[0].phys.as_tuple())
+    eager_v = sv.volume_rhs(q, geo, D, rr, tr, phys)
+    eager_mu = sv.volume_rhs_adjoint(q, geo, D, lam, phys)
+    plan.execute()
+    eager_b = [b["rhs"].clone() for b in blocks]
+    out_v = torch.empty_like(q)
+    out_mu = torch.empty_like(q)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            sv.volume_rhs(q, geo, D, rr, tr, phys, out=out_v)
+            sv.volume_rhs_adjoint(q, geo, D, lam, phys, out=out_mu)
+            plan.execute()
+    torch.cuda.current_stream().wait_stream(s)
+    for replay in range(3):
+        out_v.fill_(float("nan"))
+        out_mu.fill_(float("nan"))
+        for b in blocks:
+            b["rhs"].fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out_v, eager_v), replay
+        assert torch.equal(out_mu, eager_mu), replay
+        for b, e in zip(blocks, eager_b):
+            assert torch.equal(b["rhs"], e), replay
+    plan.close()
