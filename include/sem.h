@@ -114,7 +114,8 @@ const char* sem_version(void);
  * Errors: Ne < 1 (the paper's assumption Ne >= 1), unsupported Nq, NULL
  * required pointer, only one of rho_ref/theta_ref, misaligned pointer,
  * unknown dtype -> SEM_ERR_INVALID_ARG / SEM_ERR_UNSUPPORTED before any HIP
- * call.  Allocates nothing.
+ * call.  Allocates nothing and enqueues only kernel launches (no memset or
+ * copy), so a caller may capture it into a HIP graph.
  */
 sem_status sem_volume_rhs(int32_t Ne, int32_t Nq, sem_dtype dtype,
                           const void* D, const void* geo, const void* q,
@@ -262,7 +263,8 @@ sem_status sem_batch_plan(const sem_block* blocks, int32_t nblocks, sem_dtype dt
                           sem_plan* out);
 
 /* Enqueues the whole batch as one launch: rhs of every block =
- * v(q) of that block.  Allocates nothing. */
+ * v(q) of that block.  Allocates nothing and records only the kernel launch,
+ * so a caller may capture it into a HIP graph. */
 sem_status sem_batch_execute(sem_plan plan, void* stream);
 
 /* Writes a JSON description of the plan's choices (NUL-terminated, truncated
