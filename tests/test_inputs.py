@@ -172,3 +172,38 @@ def test_curl_metrics_converge_to_analytic():
         gc = I.warped_mesh(N, 32, els, metrics="curl").geo
         errs.append(np.abs(gc[:, :9] - ga[:, :9]).max() / np.abs(ga[:, :9]).max())
     assert all(b < 0.2 * a for a, b in zip(errs, errs[1:])), errs
+
+
+def _golden(name):
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    return json.load(open(path))
+
+
+def _num(expr: str) -> float:
+    # the fixture's entries are integers, fractions and sqrt of fractions
+    from fractions import Fraction
+    neg = expr.startswith("-")
+    body = expr[1:] if neg else expr
+    if body.startswith("sqrt(") and body.endswith(")"):
+        v = math.sqrt(float(Fraction(body[5:-1])))
+    else:
+        v = float(Fraction(body))
+    return -v if neg else v
+
+
+@pytest.mark.parametrize("N", ["1", "2", "3", "4"])
+def test_gll_golden_nodes_and_weights(N):
+    g = _golden("gll_closed_forms.json")
+    n = int(N)
+    np.testing.assert_allclose(I.gll_nodes(n), [_num(v) for v in g["nodes"][N]], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(I.gll_weights(n), [_num(v) for v in g["weights"][N]], rtol=0,
+                               atol=1e-15)
+
+
+@pytest.mark.parametrize("N", ["1", "2"])
+def test_diff_matrix_golden(N):
+    g = _golden("gll_closed_forms.json")
+    ref = np.array([[_num(v) for v in row] for row in g["diff_matrix"][N]])
+    np.testing.assert_allclose(I.diff_matrix(int(N)), ref, rtol=0, atol=1e-14)
