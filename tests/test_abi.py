@@ -229,3 +229,45 @@ def test_last_error_is_per_thread(L, sv):
     t1.start(); t2.start(); t1.join(); t2.join()
     assert seen["a"][0] == sv.SEM_ERR_INVALID_ARG and "Ne = 0" in seen["a"][1]
     assert seen["b"][0] == sv.SEM_ERR_UNSUPPORTED and "Nq = 11" in seen["b"][1]
+
+
+C_CLIENT = r"""
+#include <stdio.h>
+#include <string.h>
+#include "sem.h"
+int main(void)
+{
+    sem_phys ph = {1e5, 1.4, 287.0, 9.81};
+    sem_tile tiles[64];
+    int n = sem_tile_options(SEM_F64, 8, tiles, 64);
+    sem_status st = sem_volume_rhs(0, 8, SEM_F64, (void*)0x10000, (void*)0x20000, (void*)0x30000,
+                                   NULL, NULL, &ph, (void*)0x40000, 0, NULL);
+    printf("%s|%d|%d|%s\n", sem_version(), n, (int)st, sem_last_error());
+    return (n > 0 && st == SEM_ERR_INVALID_ARG) ? 0 : 1;
+}
+"""
+
+
+def test_c_client_compiles_links_and_calls(L, tmp_path):
+    """include/sem.h compiles as C99 (and C++11) and a C program linked
+    against libsem.so calls through it (host-side validation only)."""
+    import shutil
+    import subprocess
+    from paper_1604_08501_amd import semvol
+    if not shutil.which("gcc") or not shutil.which("g++"):
+        pytest.skip("no host C compiler")
+    src = tmp_path / "client.c"
+    src.write_text(C_CLIENT)
+    inc = os.path.join(ROOT, "include")
+    libdir = os.path.dirname(semvol.LIB_PATH)
+    exe = tmp_path / "client"
+    subprocess.run(["g++", "-std=c++11", "-Wall", "-Wextra", "-pedantic", "-fsyntax-only", "-x",
+                    "c++", f"-I{inc}", str(src)], check=True)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", f"-I{inc}", str(src),
+                    f"-L{libdir}", "-l:libsem.so", f"-Wl,-rpath,{libdir}", "-o", str(exe)],
+                   check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    version, n, status, msg = r.stdout.strip().split("|", 3)
+    assert version.startswith("semvol") and int(n) > 0
+    assert int(status) == -1 and "Ne = 0" in msg
