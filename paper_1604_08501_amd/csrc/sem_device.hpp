@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace semk {
 
 struct Phys {
@@ -192,12 +194,34 @@ constexpr int alias_max_nodes_per_thread()
 // A thread of a FULL tile that handles more than one node keeps 1/J and the
 // gravity source of its nodes in LDS (two extra values per node) instead of
 // register arrays, so that its node loop need not be unrolled.
+// The r contraction runs in registers, with the r line's fluxes exchanged
+// between the lanes of a wave (DPP lane permutations), when an r line is 2, 4
+// or 8 adjacent lanes (Nq = 2, 4, 8; node m = i + Nq j + ... sits in lane
+// m mod 64) and the tile keeps each node's partial sums in registers (ALIAS,
+// or FULL with one node per thread).  Its fluxes then never touch LDS.
+constexpr bool kRegisterR = true;
+
+template <int NQ, int EPB, int NT, int LAY, int DIRS>
+constexpr bool r_in_registers()
+{
+    return kRegisterR && (DIRS & 1) != 0 && (NQ == 2 || NQ == 4 || NQ == 8) &&
+           (LAY == ALIAS || nodes_per_thread<NQ, EPB, NT>() == 1);
+}
+
+// Directions whose fluxes a tile stages in LDS.
+template <int NQ, int EPB, int NT, int LAY, int DIRS>
+constexpr int lds_dirs()
+{
+    return r_in_registers<NQ, EPB, NT, LAY, DIRS>() ? (DIRS & ~1) : DIRS;
+}
+
 template <typename T, int NQ, int EPB, int NT, int LAY, int NF = 5, int DIRS = 7>
 constexpr int volume_tile_values_per_node()
 {
     if (LAY == ALIAS)
         return NF;
-    return ndirs<DIRS>() * NF + (nodes_per_thread<NQ, EPB, NT>() > 1 ? 2 : 0);
+    return ndirs<lds_dirs<NQ, EPB, NT, LAY, DIRS>()>() * NF +
+           (nodes_per_thread<NQ, EPB, NT>() > 1 ? 2 : 0);
 }
 
 // LDS bytes a forward tile needs: D plus the staged values of every node.
@@ -375,6 +399,73 @@ __device__ __forceinline__ void contract_dir(const T* __restrict__ sD, const T* 
         contract<T, NQ, M, NF, UNR>(sD, Fd + i + NQ * j, k, NQ2, acc);
 }
 
+// Value of lane (this lane with its index bits permuted by CTRL) within the
+// same row of 16 lanes: CTRL is a DPP control (quad_perm or row_half_mirror).
+// 64-bit values move as two 32-bit halves.
+template <int CTRL, typename T>
+__device__ __forceinline__ T lane_perm(T v)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(
+            T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+    } else {
+        const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+        const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, false);
+        const unsigned hi =
+            (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+        return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+    }
+}
+
+constexpr int kQuadXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kQuadXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kQuadXor3 = 0x1B;        // quad_perm [3, 2, 1, 0]
+constexpr int kHalfRowMirror = 0x141;  // lane l of 8 <- lane 7 - l = l ^ 7
+
+// acc[b] += sum_n D[i][n] F_b(n) along an r line held one node per lane
+// (lanes i = 0..NQ-1 of an aligned group): lane i ^ x for x = 0..NQ-1 are
+// visited with quad permutations (x = 1, 2, 3) and the half-row mirror
+// (x = 7, then 6, 5, 4).  f holds this lane's own fluxes.
+template <typename T, int NQ, int NF>
+__device__ __forceinline__ void contract_r_lanes(const T* __restrict__ sD, const T (&f)[NF], int i,
+                                                 T (&acc)[NF])
+{
+    static_assert(NQ == 2 || NQ == 4 || NQ == 8, "r lines of 2, 4 or 8 lanes");
+    const T* __restrict__ Di = sD + i * NQ;
+    auto add = [&](const T (&g)[NF], int x) {
+        const T dn = Di[i ^ x];
+#pragma unroll
+        for (int b = 0; b < NF; ++b)
+            acc[b] += dn * g[b];
+    };
+    auto perm = [&](const T (&src)[NF], T (&dst)[NF], auto ctrl) {
+#pragma unroll
+        for (int b = 0; b < NF; ++b)
+            dst[b] = lane_perm<decltype(ctrl)::value>(src[b]);
+    };
+    T g[NF];
+    add(f, 0);
+    perm(f, g, std::integral_constant<int, kQuadXor1>{});
+    add(g, 1);
+    if constexpr (NQ >= 4) {
+        perm(f, g, std::integral_constant<int, kQuadXor2>{});
+        add(g, 2);
+        perm(f, g, std::integral_constant<int, kQuadXor3>{});
+        add(g, 3);
+    }
+    if constexpr (NQ == 8) {
+        T h[NF];
+        perm(f, h, std::integral_constant<int, kHalfRowMirror>{});
+        add(h, 7);
+        perm(h, g, std::integral_constant<int, kQuadXor1>{});
+        add(g, 6);
+        perm(h, g, std::integral_constant<int, kQuadXor2>{});
+        add(g, 5);
+        perm(h, g, std::integral_constant<int, kQuadXor3>{});
+        add(g, 4);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Forward tile: EPB elements starting at e0, of which the first ne exist.
 // ---------------------------------------------------------------------------
@@ -389,7 +480,9 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
     constexpr int NODES = EPB * M;
     constexpr int NPT = nodes_per_thread<NQ, EPB, NT>();
     constexpr int VPN = volume_tile_values_per_node<T, NQ, EPB, NT, FULL, NF, DIRS>();
-    constexpr int SCAL = ndirs<DIRS>() * NF;   // offset of the staged 1/J and source
+    constexpr bool RREG = r_in_registers<NQ, EPB, NT, FULL, DIRS>();
+    constexpr int LD = lds_dirs<NQ, EPB, NT, FULL, DIRS>();   // directions staged in LDS
+    constexpr int SCAL = ndirs<LD>() * NF;    // offset of the staged 1/J and source
     static_assert(!RK || NPT == 1, "a fused Runge-Kutta stage needs one node per thread");
     T* __restrict__ sD = smem;
     T* __restrict__ sF = smem + Shape<NQ>::template d_slots<T>();
@@ -397,26 +490,34 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
 
     for (int x = tid; x < NQ2; x += NT)
         sD[x] = B.D[x];
+    if constexpr (RREG)
+        __syncthreads();   // phase 1 applies D along r
 
     RkNode<T, RK> rn;
     // phase 1 for tile node t: pointwise work and the active directions'
-    // fluxes into LDS; returns 1/J and the source
-    auto phase1 = [&](int t, T& jinv, T& src) {
+    // fluxes into LDS (the r contraction itself when it runs in registers,
+    // into accr); returns 1/J and the source
+    auto phase1 = [&](int t, T& jinv, T& src, T (&accr)[NF]) {
         const int es = t / M;
         const int m = t - es * M;
         NodeState<T, NF> st;
         load_node<T, M, NF, DIRS, GEOE>(B, ph, e0 + es, m, st);
         rn.load(B, rk, e0 + es, m, M, st);
         T* __restrict__ F = sF + es * (VPN * M) + m;
+        if constexpr (RREG) {
+            T fr[NF];
+            put_flux<T, 1, NF>(st, 0, fr);
+            contract_r_lanes<T, NQ, NF>(sD, fr, m % NQ, accr);
+        }
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-            if ((DIRS >> d) & 1)
-                put_flux<T, M, NF>(st, d, F + dir_slot<DIRS>(d) * (NF * M));
+            if ((LD >> d) & 1)
+                put_flux<T, M, NF>(st, d, F + dir_slot<LD>(d) * (NF * M));
         jinv = st.jinv;
         src = st.src;
     };
     // phase 2 for tile node t: D along the active directions out of LDS
-    auto phase2 = [&](int t, T jinv, T src) {
+    auto phase2 = [&](int t, T jinv, T src, const T (&accr)[NF]) {
         const int es = t / M;
         const int m = t - es * M;
         const int i = m % NQ;
@@ -426,11 +527,11 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
         T acc[NF];
 #pragma unroll
         for (int b = 0; b < NF; ++b)
-            acc[b] = (T)0;
+            acc[b] = accr[b];
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-            if ((DIRS >> d) & 1)
-                contract_dir<T, NQ, M, NF, UNR>(sD, Fe + dir_slot<DIRS>(d) * (NF * M), d, i, j, k,
+            if ((LD >> d) & 1)
+                contract_dir<T, NQ, M, NF, UNR>(sD, Fe + dir_slot<LD>(d) * (NF * M), d, i, j, k,
                                                 acc);
         store_node<T, M, NF, ACC, RK>(B, rk, e0 + es, m, acc, jinv, src, rn);
     };
@@ -438,17 +539,25 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
     if constexpr (NPT == 1) {
         const bool live = tid < NODES && tid / M < ne;
         T jinv = (T)0, src = (T)0;
+        T accr[NF];
+#pragma unroll
+        for (int b = 0; b < NF; ++b)
+            accr[b] = (T)0;
         if (live)
-            phase1(tid, jinv, src);
+            phase1(tid, jinv, src, accr);
         __syncthreads();
         if (live)
-            phase2(tid, jinv, src);
+            phase2(tid, jinv, src, accr);
     } else {
 #pragma unroll 1
         for (int t = tid; t < NODES; t += NT) {
             if (t / M < ne) {
                 T jinv, src;
-                phase1(t, jinv, src);
+                T accr[NF];   // stays zero: several nodes per thread keep r in LDS
+#pragma unroll
+                for (int b = 0; b < NF; ++b)
+                    accr[b] = (T)0;
+                phase1(t, jinv, src, accr);
                 const int es = t / M;
                 T* S = sF + es * (VPN * M) + SCAL * M + (t - es * M);
                 S[0] = jinv;
@@ -461,7 +570,8 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
             if (t / M < ne) {
                 const int es = t / M;
                 const T* S = sF + es * (VPN * M) + SCAL * M + (t - es * M);
-                phase2(t, S[0], S[M]);
+                const T zero[NF] = {};
+                phase2(t, S[0], S[M], zero);
             }
         }
     }
@@ -483,8 +593,12 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
     T* __restrict__ sF = smem + Shape<NQ>::template d_slots<T>();
     const int tid = threadIdx.x;
 
+    constexpr bool RREG = r_in_registers<NQ, EPB, NT, ALIAS, DIRS>();
+    constexpr int LD = lds_dirs<NQ, EPB, NT, ALIAS, DIRS>();   // directions staged in LDS
     for (int x = tid; x < NQ2; x += NT)
         sD[x] = B.D[x];
+    if constexpr (RREG)
+        __syncthreads();   // D along r is applied before any LDS pass
 
     NodeState<T, NF> st[NPT];
     RkNode<T, RK> rn[NPT];
@@ -503,11 +617,21 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
             rn[p].load(B, rk, e0 + es, t - es * M, M, st[p]);
         }
     }
+    if constexpr (RREG) {
+#pragma unroll
+        for (int p = 0; p < NPT; ++p)
+            if (live[p]) {
+                const int t = tid + p * NT;
+                T fr[NF];
+                put_flux<T, 1, NF>(st[p], 0, fr);
+                contract_r_lanes<T, NQ, NF>(sD, fr, (t - (t / M) * M) % NQ, acc[p]);
+            }
+    }
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        if (!((DIRS >> d) & 1))
+        if (!((LD >> d) & 1))
             continue;
-        if (dir_slot<DIRS>(d) > 0)
+        if (dir_slot<LD>(d) > 0)
             __syncthreads();   // every read of the previous direction is done
 #pragma unroll
         for (int p = 0; p < NPT; ++p)
