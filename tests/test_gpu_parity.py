@@ -346,7 +346,7 @@ def test_rk3_graph(sv, oracle_mod, dtype, separate):
 EXT_EPB = {2: 64, 3: 16, 4: 8, 5: 4, 6: 2}
 
 
-@pytest.mark.parametrize("Nq", [2, 3, 4, 5, 6, 8, 9, 10, 12, 16])
+@pytest.mark.parametrize("Nq", [2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16])
 @pytest.mark.parametrize("nf,dirs", [(5, 3), (8, 3), (8, 7), (5, 7)])
 def test_ext_vs_oracle(sv, oracle_mod, Nq, nf, dirs):
     Ne = 2 * EXT_EPB.get(Nq, 1) + 1                  # several tiles and a ragged tail
@@ -396,7 +396,7 @@ def test_ext_paper_constants(sv, oracle_mod):
 # ---------------------------------------------------------------------------
 # Per-element metric terms (affine elements)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("Nq", [2, 3, 4, 5, 8, 10, 12, 16])
+@pytest.mark.parametrize("Nq", [2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16])
 def test_affine_per_element_geometry(sv, oracle_mod, Nq):
     n_side = 3 if Nq <= 8 else 2
     w = I.affine_workload(N=Nq - 1, n_side=n_side, k=130 + Nq, with_adjoint=False)
@@ -438,7 +438,7 @@ def test_curl_metrics_free_stream_on_gpu(sv, oracle_mod, N):
 # ---------------------------------------------------------------------------
 # Optimisation ladder of the paper's benchmark kernel (FP32, 8 fields, r+s)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("Nq", [2, 3, 4, 8, 12, 16])
+@pytest.mark.parametrize("Nq", [2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16])
 def test_ladder_levels_vs_oracle(sv, oracle_mod, Nq):
     """Every level of the ladder computes the paper's kernel: rhs += v with 8
     fields, the r and s terms, p0 = 1, gamma = 1.4, R = 1, no source."""
