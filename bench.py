@@ -20,7 +20,8 @@ metric form on an affine N=7 mesh of 32768 elements against the per-node
 form of the same mesh, and the optimisation ladder of the paper's
 benchmark kernel (levels 1-6) at Nq = 8 on the Table 2 shape.
 The warm-up (30 launches by default) lets the clock settle before the timed
-launches, so the rate is the sustained one.
+launches, so the rate is the sustained one; the secondary legs, whose
+launches are short, also keep launching for SETTLE_S before timing.
 
 Prints one JSON line.  ``roofline`` prices the FP64 volume kernel against
 the 8 TB/s HBM peak using the algorithmic bytes per node (176 B in FP64,
@@ -79,11 +80,23 @@ def measured_traffic(kernel_key: str):
     return ent.get("bytes_per_launch") if ent else None
 
 
-def time_launches(fn, steps: int, warmup: int, stream):
+# The shader clock ramps up over the first milliseconds of load after an idle
+# spell (such as the host-side generation of a leg's inputs), so the
+# secondary legs, whose launches last tens of microseconds, keep launching
+# for this long after their warm-up launches before the timed ones.
+SETTLE_S = 0.05
+
+
+def time_launches(fn, steps: int, warmup: int, stream, settle_s: float = 0.0):
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < settle_s:
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -120,7 +133,7 @@ def bench_batch_and_rk3(sv, I, steps: int, warmup: int, stream):
                                rhs=L[off:off + sz].view(w.q.shape)))
             off += sz
         plan = sv.BatchPlan(blocks, ws[0].phys.as_tuple(), autotune=True)
-        ms_rhs, _ = time_launches(plan.execute, steps, warmup, stream)
+        ms_rhs, _ = time_launches(plan.execute, steps, warmup, stream, SETTLE_S)
         q0 = q_n.clone()
         bpn = BYTES_PER_NODE[tag]
         esz = 8 if tag == "f64" else 4
@@ -129,7 +142,7 @@ def bench_batch_and_rk3(sv, I, steps: int, warmup: int, stream):
             q_n.copy_(q0)
             g = sv.RK3Graph(blocks, q_n, q_1, q_2, L, 1e-3, ws[0].phys.as_tuple(), autotune=True,
                             separate_stages=separate)
-            ms_rk, _ = time_launches(g.step, steps, warmup, stream)
+            ms_rk, _ = time_launches(g.step, steps, warmup, stream, SETTLE_S)
             if separate:
                 # 3 x (RHS + axpby); axpby reads 3 (2 in stage 1) and writes 1 value per dof
                 rk_bytes = 3 * bpn * nodes + (4 + 4 + 3) * esz * n
@@ -160,7 +173,7 @@ def bench_adjoint(sv, I, steps: int, warmup: int, stream):
         q, geo, D, lam = t(src.q), t(src.geo), t(src.D), t(src.lam)
         mu = torch.empty_like(q)
         ms, _ = time_launches(lambda: sv.volume_rhs_adjoint(q, geo, D, lam, w.phys.as_tuple(), out=mu),
-                              steps, warmup, stream)
+                              steps, warmup, stream, SETTLE_S)
         esz = 8 if tag == "f64" else 4
         out[tag] = {"ms": ms, "el_s": w.Ne / (ms * 1e-3),
                     "GBs": 25 * esz * nodes / (ms * 1e-3) / 1e9}
@@ -197,7 +210,7 @@ def bench_paper_table2(sv, I, steps: int, warmup: int, stream):
         for name, dirs, geo_words in (("rs", 3, 7), ("rst", 7, 10)):
             ms, _ = time_launches(lambda: sv.volume_rhs_ext(q, geo, D, None, None, phys, dirs=dirs,
                                                             out=rhs, accumulate=True),
-                                  steps, warmup, stream)
+                                  steps, warmup, stream, SETTLE_S)
             # per node: q 8 + metric terms of the used directions and 1/J read,
             # rhs 8 read and 8 written, 4 bytes each
             byt = (8 + geo_words + 16) * 4 * nodes
@@ -236,7 +249,8 @@ def bench_ladder(sv, I, steps: int, warmup: int, stream):
     for level in range(1, sv.LADDER_LEVELS + 1):
         n_steps = steps if level >= 3 else max(3, steps // 10)
         ms, _ = time_launches(lambda: sv.volume_rhs_ladder(level, q, geo, D, phys, out=rhs),
-                              n_steps, min(warmup, 3) if level < 3 else warmup, stream)
+                              n_steps, min(warmup, 3) if level < 3 else warmup, stream,
+                              SETTLE_S if level >= 3 else 0.0)
         base = base or ms
         out["levels"][str(level)] = {"ms": ms, "speedup_vs_level1": base / ms,
                                      "GBs_final_kernel_bytes": byt / (ms * 1e-3) / 1e9}
@@ -265,9 +279,9 @@ benchmark kernel (levels 1-6) at Nq = 8 on the Table 2 shape.
         o1, o2 = torch.empty_like(q), torch.empty_like(q)
         ph = w.phys.as_tuple()
         ms_node, _ = time_launches(lambda: sv.volume_rhs(q, geo, D, rr, tr, ph, out=o1),
-                                   steps, warmup, stream)
+                                   steps, warmup, stream, SETTLE_S)
         ms_elem, _ = time_launches(lambda: sv.volume_rhs_affine(q, g_el, D, rr, tr, ph, out=o2),
-                                   steps, warmup, stream)
+                                   steps, warmup, stream, SETTLE_S)
         torch.cuda.synchronize()
         diff = float(I.rel_err_per_field(o2.cpu().numpy(), o1.cpu().numpy()).max())
         esz = 8 if tag == "f64" else 4

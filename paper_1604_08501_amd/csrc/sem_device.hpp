@@ -673,51 +673,88 @@ __device__ __forceinline__ void volume_tile(const BlockPtrs<T>& B, int64_t e0, i
 }
 
 // ---------------------------------------------------------------------------
-// r+s tile of one element walked a k-slice at a time: lanes over the (i, j)
-// nodes of a slice, k sequential (the work mapping of the paper's own
-// kernel).  The r and s contractions of slice k need only slice k's fluxes,
-// so the LDS holds 2 NF Nq^2 values instead of the whole element's, which
-// keeps large elements (Nq = 12, 16) resident several workgroups per CU and
-// fits FP64 at Nq = 16.
+// r+s tile over a group of k-slices of one element: lanes over the (i, j, k)
+// nodes of S consecutive slices.  The r and s contractions of slice k need
+// only slice k's fluxes, so every slice group is an independent tile: the
+// LDS holds 2 NF S Nq^2 values instead of the whole element's (large
+// elements, Nq = 12 and 16, stay resident several workgroups per CU, FP64 at
+// Nq = 16 fits), and an element spreads over Nq / S workgroups, which keeps
+// the chip busy on the few large elements of a fixed node count.
 // ---------------------------------------------------------------------------
-template <int NQ>
+// Slices per workgroup and unroll of the contraction loop, per precision and
+// Nq, as measured on MI355X (8 fields, r+s, the fixed-node-count shapes):
+// FP32 at Nq = 12 takes two slices (288 of 320 lanes live), every other
+// shape one slice.  Fewer contraction terms are kept in flight where the
+// whole loop would not fit the register budget (FP64 at Nq = 16, four waves
+// per SIMD; FP32 with 5 fields at Nq = 16, eight waves).
+template <typename T, int NQ>
+constexpr int slab_slices()
+{
+    return (sizeof(T) == 4 && NQ == 12) ? 2 : 1;
+}
+
+template <typename T, int NQ, int NF>
+constexpr int slab_unroll()
+{
+    if constexpr (sizeof(T) == 4)
+        return NQ == 12 ? 2 : (NF == 8 ? NQ : 8);
+    else
+        return NQ == 16 ? 8 : NQ;
+}
+
+template <typename T, int NQ>
 constexpr int slab_threads()
 {
-    return ((NQ * NQ + 63) / 64) * 64;
+    return ((slab_slices<T, NQ>() * NQ * NQ + 63) / 64) * 64;
 }
 
 template <typename T, int NQ, int NF>
 constexpr int volume_slab_lds_values()
 {
-    return Shape<NQ>::template d_slots<T>() + 2 * NF * NQ * NQ;
+    return Shape<NQ>::template d_slots<T>() + 2 * NF * slab_slices<T, NQ>() * NQ * NQ;
 }
 
+// Slice groups g = 0 .. Ne Nq / S - 1, group g covering slices
+// k0 .. k0 + S - 1 of element g / (Nq / S), k0 = S (g mod Nq / S); the
+// workgroups stride over them.
 template <typename T, int NQ, bool ACC, int NF, bool GEOE>
-__device__ __forceinline__ void volume_tile_slab(const BlockPtrs<T>& B, int64_t e, const Phys& ph,
+__device__ __forceinline__ void volume_tile_slab(const BlockPtrs<T>& B, const Phys& ph,
                                                  T* __restrict__ smem)
 {
     constexpr int NQ2 = Shape<NQ>::NQ2;
     constexpr int M = Shape<NQ>::M;
-    constexpr int NT = slab_threads<NQ>();
-    // a slice row that is not a whole number of 128-byte lines shares a line
-    // with the next slice, which a cached read then serves
-    constexpr bool STREAM = (NQ2 * (int)sizeof(T)) % 128 == 0;
+    constexpr int S = slab_slices<T, NQ>();
+    constexpr int G = NQ / S;   // slice groups per element
+    constexpr int NT = slab_threads<T, NQ>();
+    constexpr int UNR = slab_unroll<T, NQ, NF>();
+    // the group's run of each array is whole 128-byte lines (streamed), or
+    // shares lines with the next group's (read through the cache)
+    constexpr bool STREAM = (S * NQ2 * (int)sizeof(T)) % 128 == 0;
     T* __restrict__ sD = smem;
     T* __restrict__ sF = smem + Shape<NQ>::template d_slots<T>();
     const int tid = threadIdx.x;
     for (int x = tid; x < NQ2; x += NT)
         sD[x] = B.D[x];
-    const bool live = tid < NQ2;
-    const int i = tid % NQ, j = tid / NQ;
+    const bool live = tid < S * NQ2;
+    const int ks = tid / NQ2;              // slice within the group
+    const int ij = tid - ks * NQ2;
+    const int i = ij % NQ, j = ij / NQ;
+    T* __restrict__ sFr = sF + ks * (2 * NF * NQ2);
+    T* __restrict__ sFs = sFr + NF * NQ2;
     const RkStage no_rk{0.0, 0.0, 0.0};
     const RkNode<T, false> no_rn{};
+    const int64_t groups = B.Ne * G;
 #pragma unroll 1
-    for (int k = 0; k < NQ; ++k) {
+    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int64_t e = g / G;
+        const int m = tid + NQ2 * S * (int)(g - e * G);
         NodeState<T, NF> st;
+        if (g != (int64_t)blockIdx.x)
+            __syncthreads();   // the previous group's reads of the slice buffer are done
         if (live) {
-            load_node<T, M, NF, 3, GEOE, STREAM>(B, ph, e, tid + NQ2 * k, st);
-            put_flux<T, NQ2, NF>(st, 0, sF + tid);
-            put_flux<T, NQ2, NF>(st, 1, sF + NF * NQ2 + tid);
+            load_node<T, M, NF, 3, GEOE, STREAM>(B, ph, e, m, st);
+            put_flux<T, NQ2, NF>(st, 0, sFr + ij);
+            put_flux<T, NQ2, NF>(st, 1, sFs + ij);
         }
         __syncthreads();
         if (live) {
@@ -725,12 +762,10 @@ __device__ __forceinline__ void volume_tile_slab(const BlockPtrs<T>& B, int64_t 
 #pragma unroll
             for (int b = 0; b < NF; ++b)
                 acc[b] = (T)0;
-            contract<T, NQ, NQ2, NF>(sD, sF + NQ * j, i, 1, acc);
-            contract<T, NQ, NQ2, NF>(sD, sF + NF * NQ2 + i, j, NQ, acc);
-            store_node<T, M, NF, ACC, false, STREAM>(B, no_rk, e, tid + NQ2 * k, acc, st.jinv, st.src,
-                                                     no_rn);
+            contract<T, NQ, NQ2, NF, UNR>(sD, sFr + NQ * j, i, 1, acc);
+            contract<T, NQ, NQ2, NF, UNR>(sD, sFs + i, j, NQ, acc);
+            store_node<T, M, NF, ACC, false, STREAM>(B, no_rk, e, m, acc, st.jinv, st.src, no_rn);
         }
-        __syncthreads();   // the slice buffer is rewritten by the next slice
     }
 }
 
