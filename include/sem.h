@@ -146,11 +146,14 @@ int32_t sem_tile_options(sem_dtype dtype, int32_t Nq, sem_tile* out, int32_t cap
  *             q, rhs: [Ne][nfields][Nq^3]
  *   dirs      SEM_DIR_R | SEM_DIR_S, or SEM_DIR_R | SEM_DIR_S | SEM_DIR_T; the
  *             geo slots of an excluded direction are not read
- *   Nq        2..10, 12 or 16 (in FP64, Nq = 16 with r+s+t does not fit the
- *             160 KB LDS)
+ *   Nq        2..10, 12 or 16
  * All other arguments, the gravity source and the reference state are as for
  * sem_volume_rhs.  Each (Nq, nfields, dirs) has one built-in tile shape; r+s at
- * Nq >= 12 walks each element a k-slice at a time.
+ * Nq >= 12 tiles each element by groups of k-slices.  r+s+t at Nq = 16 is two
+ * launches on `stream`: the r+s term with the source (as requested, overwrite
+ * or accumulate), then the t term added to it; the result is the same up to
+ * rounding order (the t sum is added to the finished r+s value instead of
+ * being summed with it before the 1/J factor).
  * Errors: unsupported nfields / dirs / Nq -> SEM_ERR_UNSUPPORTED; otherwise as
  * sem_volume_rhs.  Allocates nothing.
  */
@@ -198,9 +201,9 @@ sem_status sem_volume_rhs_ladder(int32_t level, int32_t Ne, int32_t Nq, const vo
  * reference-to-physical map; for x = A xi + b they do not vary inside the
  * element):
  *   geo_elem  [Ne][10], slot 3*d + a = g_{a d}, slot 9 = 1/J, one set per element
- * Every other argument as for sem_volume_rhs; Nq 2..10, 12, 16 (FP64 Nq = 16
- * excluded by the LDS).  The per-node metric arrays are 10 of the 22 values a
- * node moves in FP64; this form moves 12.
+ * Every other argument as for sem_volume_rhs; Nq 2..10, 12, 16 (Nq = 16 runs
+ * as the two launches described for sem_volume_rhs_ext).  The per-node metric
+ * arrays are 10 of the 22 values a node moves in FP64; this form moves 12.
  * Errors as for sem_volume_rhs.  Allocates nothing.
  */
 sem_status sem_volume_rhs_affine(int32_t Ne, int32_t Nq, sem_dtype dtype, const void* D,

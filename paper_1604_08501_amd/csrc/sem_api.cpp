@@ -269,7 +269,7 @@ extern "C" sem_status sem_volume_rhs_ext(int32_t Ne, int32_t Nq, sem_dtype dtype
     if (!ok)
         return fail(SEM_ERR_UNSUPPORTED,
                     "Nq = %d with %d fields and dirs = %u is not compiled for this dtype "
-                    "(Nq 2..10, 12, 16 where the LDS allows)", Nq, nfields, dirs);
+                    "(Nq 2..10, 12, 16)", Nq, nfields, dirs);
     SEM_TRY(check_volume_ptrs(dtype, D, geo, q, rho_ref, theta_ref, phys, rhs));
     if (nfields == 5 && dirs == 7 && Nq <= kMaxNq)
         return sem_volume_rhs(Ne, Nq, dtype, D, geo, q, rho_ref, theta_ref, phys, rhs, accumulate,
@@ -329,7 +329,7 @@ extern "C" sem_status sem_volume_rhs_affine(int32_t Ne, int32_t Nq, sem_dtype dt
                                      : semh::affine_supported<float>(Nq);
     if (!ok)
         return fail(SEM_ERR_UNSUPPORTED, "Nq = %d is not compiled for per-element metric terms "
-                                         "in this dtype (Nq 2..10, 12, 16 where the LDS allows)",
+                                         "in this dtype (Nq 2..10, 12, 16)",
                     Nq);
     SEM_TRY(check_volume_ptrs(dtype, D, geo_elem, q, rho_ref, theta_ref, phys, rhs));
     const semk::Phys ph = to_phys(phys);

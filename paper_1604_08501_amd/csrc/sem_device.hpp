@@ -313,8 +313,10 @@ struct NodeState {
 // GEOE: the metric terms are given once per element (affine elements,
 // geo[e][10]) instead of at every node (geo[e][10][Nq^3]).  STREAM = false
 // reads through the cache (for tiles whose consecutive accesses share cache
-// lines).
-template <typename T, int M, int NF, int DIRS, bool GEOE = false, bool STREAM = true>
+// lines).  SRC = false leaves the gravity source out (src = 0, rho_ref not
+// read), for a pass that adds one direction's term to a finished rhs.
+template <typename T, int M, int NF, int DIRS, bool GEOE = false, bool STREAM = true,
+          bool SRC = true>
 __device__ __forceinline__ void load_node(const BlockPtrs<T>& B, const Phys& ph, int64_t e, int m,
                                           NodeState<T, NF>& st)
 {
@@ -342,10 +344,11 @@ __device__ __forceinline__ void load_node(const BlockPtrs<T>& B, const Phys& ph,
     T rr = (T)0;
     double thr = 0.0;
     if (has_ref) {
-        rr = ld(B.rho_ref + e * M + m);
+        if constexpr (SRC)
+            rr = ld(B.rho_ref + e * M + m);
         thr = ld(B.theta_ref + e * M + m);
     }
-    st.src = -(T)ph.grav * (rho - rr);
+    st.src = SRC ? -(T)ph.grav * (rho - rr) : (T)0;
     st.pp = Pressure<T>::eval(st.Th, has_ref, thr, ph);
     st.rinv = (T)1 / rho;
 }
@@ -766,6 +769,73 @@ __device__ __forceinline__ void volume_tile_slab(const BlockPtrs<T>& B, const Ph
             contract<T, NQ, NQ2, NF, UNR>(sD, sFs + i, j, NQ, acc);
             store_node<T, M, NF, ACC, false, STREAM>(B, no_rk, e, m, acc, st.jinv, st.src, no_rn);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// t term of large elements as a pass of its own: rhs += -(1/J) D_t F^t, with
+// no source (the r+s pass before it wrote the rest).  The t contraction
+// couples only the Nq nodes of one (i, j) column, so a tile is a block of
+// J rows of columns, (i, j0 .. j0 + J - 1, all k): Nq^2 J nodes, one per
+// lane, their t fluxes in LDS.  For each k the block's nodes are J Nq
+// consecutive values of every array.
+// ---------------------------------------------------------------------------
+template <typename T, int NQ>
+constexpr int tcol_rows()
+{
+    return 2;
+}
+
+template <typename T, int NQ>
+constexpr int tcol_threads()
+{
+    return NQ * NQ * tcol_rows<T, NQ>();
+}
+
+template <typename T, int NQ, int NF>
+constexpr int volume_tcol_lds_values()
+{
+    return Shape<NQ>::template d_slots<T>() + NF * tcol_threads<T, NQ>();
+}
+
+template <typename T, int NQ, int NF, bool GEOE>
+__device__ __forceinline__ void volume_tile_tcol(const BlockPtrs<T>& B, const Phys& ph,
+                                                 T* __restrict__ smem)
+{
+    constexpr int NQ2 = Shape<NQ>::NQ2;
+    constexpr int M = Shape<NQ>::M;
+    constexpr int J = tcol_rows<T, NQ>();
+    constexpr int G = NQ / J;            // column blocks per element
+    constexpr int NT = tcol_threads<T, NQ>();
+    constexpr int ROW = J * NQ;          // nodes of one k in the block
+    constexpr bool STREAM = (ROW * (int)sizeof(T)) % 128 == 0;
+    static_assert(NQ % J == 0, "column blocks tile the element");
+    T* __restrict__ sD = smem;
+    T* __restrict__ sF = smem + Shape<NQ>::template d_slots<T>();
+    const int tid = threadIdx.x;
+    for (int x = tid; x < NQ2; x += NT)
+        sD[x] = B.D[x];
+    const int k = tid / ROW;
+    const int c = tid - k * ROW;         // column within the block: i + Nq jj
+    const RkStage no_rk{0.0, 0.0, 0.0};
+    const RkNode<T, false> no_rn{};
+    const int64_t groups = B.Ne * G;
+#pragma unroll 1
+    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int64_t e = g / G;
+        const int m = NQ * J * (int)(g - e * G) + c + NQ2 * k;
+        NodeState<T, NF> st;
+        if (g != (int64_t)blockIdx.x)
+            __syncthreads();   // the previous block's reads of the flux buffer are done
+        load_node<T, M, NF, 4, GEOE, STREAM, false>(B, ph, e, m, st);
+        put_flux<T, NT, NF>(st, 2, sF + tid);
+        __syncthreads();
+        T acc[NF];
+#pragma unroll
+        for (int b = 0; b < NF; ++b)
+            acc[b] = (T)0;
+        contract<T, NQ, NT, NF, (sizeof(T) == 4 ? NQ : 8)>(sD, sF + c, k, ROW, acc);
+        store_node<T, M, NF, true, false, STREAM>(B, no_rk, e, m, acc, st.jinv, (T)0, no_rn);
     }
 }
 

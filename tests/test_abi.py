@@ -170,8 +170,7 @@ def test_ext_validation(L, sv):
     assert ext(dirs=5) == sv.SEM_ERR_UNSUPPORTED
     assert ext(dirs=1) == sv.SEM_ERR_UNSUPPORTED
     assert ext(Nq=11) == sv.SEM_ERR_UNSUPPORTED
-    assert ext(Nq=16, dt=0, dirs=7) == sv.SEM_ERR_UNSUPPORTED   # FP64 r+s+t at Nq = 16 exceeds the LDS
-    assert b"Nq = 16" in L.sem_last_error()
+    assert b"Nq = 11" in L.sem_last_error()
     assert ext(q=3 * A + 2) == sv.SEM_ERR_INVALID_ARG      # misaligned FP32 array
     assert ext(rhs=3 * A) == sv.SEM_ERR_INVALID_ARG        # rhs aliases q
     assert ext(dt=9) == sv.SEM_ERR_INVALID_ARG
@@ -185,7 +184,6 @@ def test_affine_validation(L, sv):
                                        rhs, 0, None)
     assert aff(Ne=0) == sv.SEM_ERR_INVALID_ARG
     assert aff(Nq=11) == sv.SEM_ERR_UNSUPPORTED
-    assert aff(Nq=16) == sv.SEM_ERR_UNSUPPORTED
     assert aff(geo=None) == sv.SEM_ERR_INVALID_ARG
     assert aff(geo=2 * A + 4) == sv.SEM_ERR_INVALID_ARG
     assert aff(rhs=2 * A) == sv.SEM_ERR_INVALID_ARG
