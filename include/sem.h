@@ -153,7 +153,10 @@ int32_t sem_tile_options(sem_dtype dtype, int32_t Nq, sem_tile* out, int32_t cap
  * launches on `stream`: the r+s term with the source (as requested, overwrite
  * or accumulate), then the t term added to it; the result is the same up to
  * rounding order (the t sum is added to the finished r+s value instead of
- * being summed with it before the 1/J factor).
+ * being summed with it before the 1/J factor).  These passes launch one
+ * workgroup per tile up to a cap (2^32 work-items, or the environment
+ * variable SEM_MAX_WORKGROUPS if set lower, for tests); the workgroups then
+ * stride over the tiles.
  * Errors: unsupported nfields / dirs / Nq -> SEM_ERR_UNSUPPORTED; otherwise as
  * sem_volume_rhs.  Allocates nothing.
  */

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -374,6 +375,8 @@ sem_status time_candidate(PlanCore& p, int nq, int cap, hipStream_t s, double* u
     return SEM_OK;
 }
 
+constexpr std::chrono::milliseconds kSettle{30};
+
 // For every workgroup size and every LDS cap (the LDS of a compiled shape),
 // pick per order the fastest shape that fits under the cap, timed at that
 // cap; keep the (size, cap) whose per-order times sum lowest.  The launch's
@@ -390,6 +393,7 @@ sem_status autotune(PlanCore& p, bool use_cache, hipStream_t s)
     }
     SEM_TRY(upload_blocks(p, s));
     bool all_cached = true;
+    bool settled = false;
     double best_total = 1e300;
     int best_nt = 0, best_cap = 0;
     std::vector<OrderChoice> best_orders;
@@ -436,6 +440,16 @@ sem_status autotune(PlanCore& p, bool use_cache, hipStream_t s)
                             o.lay = v.lay;
                         }
                     double us = 0.0;
+                    if (!settled) {
+                        // the shader clock ramps up over the first milliseconds
+                        // of load; keep launching before the first timing so
+                        // that no candidate is timed on the ramp
+                        const auto t0 = std::chrono::steady_clock::now();
+                        do
+                            SEM_TRY(time_candidate(p, oc.nq, cap, s, &us));
+                        while (std::chrono::steady_clock::now() - t0 < kSettle);
+                        settled = true;
+                    }
                     SEM_TRY(time_candidate(p, oc.nq, cap, s, &us));
                     if (log_enabled())
                         fprintf(stderr, "[semvol] autotune %s nt=%d lds<=%d nq=%d epb=%d layout=%d: %.2f us\n",

@@ -373,6 +373,25 @@ def test_ext_vs_oracle(sv, oracle_mod, Nq, nf, dirs):
     assert e32.max() <= TOL32, (Nq, nf, dirs, e32)
 
 
+@pytest.mark.parametrize("Nq,dirs", [(12, 3), (16, 3), (16, 7)])
+def test_ext_strided_tiles(sv, oracle_mod, monkeypatch, Nq, dirs):
+    """The k-slice and t-column passes with fewer workgroups than tiles
+    (each workgroup then strides over several tiles): same values."""
+    monkeypatch.setenv("SEM_MAX_WORKGROUPS", "7")
+    w = I.add_tracers(I.warped_workload(N=Nq - 1, n_elements=3, k=140 + Nq))
+    phys = w.phys.as_tuple()
+    ref = oracle_mod.volume_rhs_ext(w.D, w.geo, w.q, w.rho_ref, w.theta_ref, phys, dirs=dirs)
+    out = sv.volume_rhs_ext(dev(w.q), dev(w.geo), dev(w.D), dev(w.rho_ref), dev(w.theta_ref), phys,
+                            dirs=dirs)
+    assert err(host(out), ref).max() <= TOL64
+    w32 = I.to_fp32(w)
+    u = I.upcast(w32)
+    ref32 = oracle_mod.volume_rhs_ext(u.D, u.geo, u.q, u.rho_ref, u.theta_ref, phys, dirs=dirs)
+    out32 = sv.volume_rhs_ext(dev(w32.q), dev(w32.geo), dev(w32.D), dev(w32.rho_ref),
+                              dev(w32.theta_ref), phys, dirs=dirs)
+    assert err(host(out32), ref32).max() <= TOL32
+
+
 def test_ext_paper_constants(sv, oracle_mod):
     """The paper's benchmark configuration: 8 fields, r and s only, p0 = 1,
     gamma = 1.4, R = 1, no gravity, no reference state, rhsq accumulated."""
