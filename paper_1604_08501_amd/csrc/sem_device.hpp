@@ -233,10 +233,12 @@ constexpr int volume_tile_lds_bytes()
            (int)sizeof(T);
 }
 
-// Values the fused Runge-Kutta epilogue needs at its node, gathered with the
-// rest of the node's inputs in phase 1 so that no memory round trip is left
-// for the end of the tile: the stage input q (taken from the node's state,
-// which has just been read) and, when a != 0, x.
+// The stage input q of the fused Runge-Kutta epilogue, taken from the node's
+// state when it is read.  The other epilogue input, x (when a != 0), is read
+// at the store: reading it with the state kept 5 more values per node live
+// through the tile, which pushed the two-node aliased shapes past the
+// register budget into scratch spills (FP64 RK3 step 0.969 -> 0.935 ms,
+// FP32 0.512 -> 0.500 ms without them).
 template <typename T, bool RK>
 struct RkNode {
     template <typename S>
@@ -249,26 +251,15 @@ struct RkNode {
 template <typename T>
 struct RkNode<T, true> {
     T q[5];
-    T x[5];
     template <typename S>
-    __device__ __forceinline__ void load(const BlockPtrs<T>& B, const RkStage& rk, int64_t e, int m,
-                                         int M, const S& st)
+    __device__ __forceinline__ void load(const BlockPtrs<T>&, const RkStage&, int64_t, int, int,
+                                         const S& st)
     {
         q[0] = st.rho;
         q[1] = st.U1;
         q[2] = st.U2;
         q[3] = st.U3;
         q[4] = st.Th;
-        if (rk.a != 0.0) {
-            const T* xe = B.rk_x + e * (5 * M) + m;
-#pragma unroll
-            for (int b = 0; b < 5; ++b)
-                x[b] = ld_stream(xe + b * M);
-        } else {
-#pragma unroll
-            for (int b = 0; b < 5; ++b)
-                x[b] = (T)0;
-        }
     }
 };
 
@@ -281,13 +272,20 @@ __device__ __forceinline__ void store_node(const BlockPtrs<T>& B, const RkStage&
 {
     static_assert(!RK || NF == 5, "the fused Runge-Kutta stage is for the five-field state");
     T* __restrict__ re = B.rhs + e * (NF * M) + m;
+    T x[RK ? 5 : 1];
+    if constexpr (RK) {
+        const T* xe = B.rk_x + e * (5 * M) + m;
+#pragma unroll
+        for (int b = 0; b < 5; ++b)
+            x[b] = rk.a != 0.0 ? ld_stream(xe + b * M) : (T)0;
+    }
 #pragma unroll
     for (int b = 0; b < NF; ++b) {
         T v = -jinv * acc[b];
         if (b == 3)
             v += src;
         if constexpr (RK) {
-            st_stream(re + b * M, (T)rk.a * rn.x[b] + (T)rk.b * (rn.q[b] + (T)rk.dt * v));
+            st_stream(re + b * M, (T)rk.a * x[b] + (T)rk.b * (rn.q[b] + (T)rk.dt * v));
         } else if constexpr (STREAM) {
             if constexpr (ACC)
                 v += ld_stream(re + b * M);
