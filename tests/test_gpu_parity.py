@@ -554,6 +554,24 @@ def test_full_table2_shapes(sv, oracle_mod, Nq):
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("Nq", [12, 16])
+def test_full_table2_shapes_fp64(sv, oracle_mod, Nq):
+    """FP64 at the full Table 2 size for the k-slice r+s tile and (Nq = 16)
+    the two-pass r+s+t."""
+    phys = (1.0, 1.4, 1.0, 0.0)
+    w = I.table2_workload(Nq)
+    base = np.random.default_rng(Nq).standard_normal(w.q.shape)
+    q, geo, D = dev(w.q), dev(w.geo), dev(w.D)
+    for dirs in (3, 7):
+        ref = oracle_mod.volume_rhs_ext(w.D, w.geo, w.q, None, None, phys, dirs=dirs, out=base.copy(),
+                                        accumulate=True)
+        out = dev(base.copy())
+        sv.volume_rhs_ext(q, geo, D, None, None, phys, dirs=dirs, out=out, accumulate=True)
+        e = err(host(out), ref)
+        assert e.max() <= TOL64, (Nq, dirs, e)
+
+
+@pytest.mark.slow
 def test_full_ladder_table1_shape(sv, oracle_mod):
     """Every ladder level at the Nq = 8 Table 2 shape (6912 elements)."""
     phys = (1.0, 1.4, 1.0, 0.0)
