@@ -26,7 +26,9 @@ launches are short, also keep launching for SETTLE_S before timing.
 Prints one JSON line.  ``roofline`` prices the FP64 volume kernel against
 the 8 TB/s HBM peak using the algorithmic bytes per node (176 B in FP64,
 92 B in FP32); its duration is measured with HIP events on the launch
-stream.  ``cpu_baseline`` times the CPU oracle on the host cores.
+stream.  ``copy_reference`` is the rate of a plain 2 GiB device-to-device copy
+on the same GPU, with the volume kernels' rates relative to it.
+``cpu_baseline`` times the CPU oracle on the host cores.
 """
 from __future__ import annotations
 
@@ -107,6 +109,19 @@ def time_launches(fn, steps: int, warmup: int, stream, settle_s: float = 0.0):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return start.elapsed_time(end) / steps, wall
+
+
+def copy_rate(gib: float, steps: int, warmup: int, stream, settle_s: float = 0.0):
+    """Rate of a plain device-to-device copy of `gib` GiB (bytes read + written
+    over the launch time)."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    ms, _ = time_launches(lambda: dst.copy_(src), steps, warmup, stream, settle_s)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * n * 8, "ms": ms, "GBs": 2 * n * 8 / (ms * 1e-3) / 1e9}
 
 
 def bench_batch_and_rk3(sv, I, steps: int, warmup: int, stream):
@@ -373,13 +388,9 @@ def main(argv=None):
     stream = torch.cuda.current_stream()
 
     if a.copy_probe > 0:
-        n = int(a.copy_probe * (1 << 30)) // 8
-        src = torch.ones(n, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        ms, _ = time_launches(lambda: dst.copy_(src), a.steps, a.warmup, stream)
-        moved = 2 * n * 8
-        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
-                          "ms_per_copy": ms, "copy_GBs": moved / (ms * 1e-3) / 1e9}), flush=True)
+        r = copy_rate(a.copy_probe, a.steps, a.warmup, stream)
+        print(json.dumps({"copy_probe_bytes_read": r["bytes"] // 2, "copy_probe_bytes_written":
+                          r["bytes"] // 2, "ms_per_copy": r["ms"], "copy_GBs": r["GBs"]}), flush=True)
         return 0
 
     t0 = time.perf_counter()
@@ -453,6 +464,11 @@ def main(argv=None):
                      "frac": r64["gbs"] / HBM_PEAK_GBS, "traffic": traffic},
     }
     if not a.no_extra:
+        # the same HBM moved by a plain device copy (read + write), for scale
+        c = copy_rate(2.0, 20, 5, stream, SETTLE_S)
+        line["copy_reference"] = {"workload": "device-to-device copy of 2 GiB", "GBs": c["GBs"],
+                                  "f64_vs_copy": r64["gbs"] / c["GBs"],
+                                  "f32_vs_copy": r32["gbs"] / c["GBs"]}
         line["batch_mixed_order"] = bench_batch_and_rk3(sv, I, a.steps, a.warmup, stream)
         line["adjoint"] = bench_adjoint(sv, I, a.steps, a.warmup, stream)
         line["paper_table2"] = bench_paper_table2(sv, I, a.steps, a.warmup, stream)
