@@ -660,6 +660,37 @@ def test_concurrent_host_threads_and_streams(sv, oracle_mod):
         assert err(got, ref).max() <= TOL64, w.N
 
 
+def test_two_pass_ext_inside_a_captured_graph(sv):
+    """r+s+t at Nq = 16 (a k-slice pass and a t-column pass on the caller's
+    stream) and the per-element form at Nq = 16 record into a captured graph;
+    every replay equals the eager result."""
+    w = I.add_tracers(I.warped_workload(N=15, n_elements=3, k=192))
+    phys = w.phys.as_tuple()
+    q, geo, D, rr, tr = (dev(a) for a in (w.q, w.geo, w.D, w.rho_ref, w.theta_ref))
+    wa = I.affine_workload(N=15, n_side=2, k=193, with_adjoint=False)
+    qa, ga, Da, rra, tra = (dev(a) for a in (wa.q, I.element_geo(wa.geo), wa.D, wa.rho_ref,
+                                             wa.theta_ref))
+    eager_e = sv.volume_rhs_ext(q, geo, D, rr, tr, phys, dirs=7)
+    eager_a = sv.volume_rhs_affine(qa, ga, Da, rra, tra, wa.phys.as_tuple())
+    out_e, out_a = torch.empty_like(q), torch.empty_like(qa)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            sv.volume_rhs_ext(q, geo, D, rr, tr, phys, dirs=7, out=out_e)
+            sv.volume_rhs_affine(qa, ga, Da, rra, tra, wa.phys.as_tuple(), out=out_a)
+    torch.cuda.current_stream().wait_stream(s)
+    for replay in range(3):
+        out_e.fill_(float("nan"))
+        out_a.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out_e, eager_e), replay
+        assert torch.equal(out_a, eager_a), replay
+
+
 def test_calls_inside_a_captured_graph(sv):
     """sem_volume_rhs, sem_volume_rhs_adjoint and a batch plan's launch record
     into a graph captured by the caller (they allocate nothing and record no
