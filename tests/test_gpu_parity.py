@@ -392,6 +392,27 @@ def test_ext_strided_tiles(sv, oracle_mod, monkeypatch, Nq, dirs):
     assert err(host(out32), ref32).max() <= TOL32
 
 
+@pytest.mark.parametrize("Nq", [10, 12, 16])
+def test_ext_single_element(sv, oracle_mod, Nq):
+    """One element (fewer tiles than a slice group or column block count
+    would suggest for a mesh), both direction sets, overwrite and accumulate."""
+    w = I.add_tracers(I.warped_workload(N=Nq - 1, n_elements=1, k=150 + Nq))
+    phys = w.phys.as_tuple()
+    w32 = I.to_fp32(w)
+    u = I.upcast(w32)
+    for dirs in (3, 7):
+        ref = oracle_mod.volume_rhs_ext(w.D, w.geo, w.q, w.rho_ref, w.theta_ref, phys, dirs=dirs)
+        args = (dev(w.q), dev(w.geo), dev(w.D), dev(w.rho_ref), dev(w.theta_ref), phys)
+        assert err(host(sv.volume_rhs_ext(*args, dirs=dirs)), ref).max() <= TOL64, (Nq, dirs)
+        out = dev(ref.copy())
+        sv.volume_rhs_ext(*args, dirs=dirs, out=out, accumulate=True)
+        assert err(host(out), 2 * ref).max() <= TOL64, (Nq, dirs)
+        ref32 = oracle_mod.volume_rhs_ext(u.D, u.geo, u.q, u.rho_ref, u.theta_ref, phys, dirs=dirs)
+        out32 = sv.volume_rhs_ext(dev(w32.q), dev(w32.geo), dev(w32.D), dev(w32.rho_ref),
+                                  dev(w32.theta_ref), phys, dirs=dirs)
+        assert err(host(out32), ref32).max() <= TOL32, (Nq, dirs)
+
+
 def test_ext_paper_constants(sv, oracle_mod):
     """The paper's benchmark configuration: 8 fields, r and s only, p0 = 1,
     gamma = 1.4, R = 1, no gravity, no reference state, rhsq accumulated."""
