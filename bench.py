@@ -19,9 +19,10 @@ timings on its hardware quoted beside it as context, and the per-element
 metric form on an affine N=7 mesh of 32768 elements against the per-node
 form of the same mesh, and the optimisation ladder of the paper's
 benchmark kernel (levels 1-6) at Nq = 8 on the Table 2 shape.
-The warm-up (30 launches by default) lets the clock settle before the timed
-launches, so the rate is the sustained one; the secondary legs, whose
-launches are short, also keep launching for SETTLE_S before timing.
+Timing follows the paper's method (Sec. 4): after the warm-up launches every
+leg keeps launching for at least 0.3 s, then times exactly ``--steps``
+launches with HIP events on the launch stream; the mean per launch is the
+reported rate (``ms_per_step``) and the median per launch is given beside it.
 
 Prints one JSON line.  ``roofline`` prices the FP64 volume kernel against
 the 8 TB/s HBM peak using the algorithmic bytes per node (176 B in FP64,
@@ -82,14 +83,19 @@ def measured_traffic(kernel_key: str):
     return ent.get("bytes_per_launch") if ent else None
 
 
-# The shader clock ramps up over the first milliseconds of load after an idle
-# spell (such as the host-side generation of a leg's inputs), so the
-# secondary legs, whose launches last tens of microseconds, keep launching
-# for this long after their warm-up launches before the timed ones.
-SETTLE_S = 0.05
+# The paper's timing method (Sec. 4): after warm-up, keep launching for at
+# least 0.3 s before the timed launches.  The shader clock ramps up over the
+# first milliseconds of load after an idle spell (such as the host-side
+# generation of a leg's inputs) and settles under sustained load, so every
+# leg, the headline one included, times launches at the settled clock.
+SETTLE_S = 0.3
 
 
-def time_launches(fn, steps: int, warmup: int, stream, settle_s: float = 0.0):
+def time_launches(fn, steps: int, warmup: int, stream, settle_s: float = SETTLE_S):
+    """Warm up, keep launching for settle_s, then time exactly `steps`
+    launches with one HIP event before each launch and one after the last,
+    all on `stream`.  Returns (mean ms per launch, median ms per launch, wall
+    seconds of the timed launches)."""
     import torch
     for _ in range(warmup):
         fn()
@@ -99,26 +105,28 @@ def time_launches(fn, steps: int, warmup: int, stream, settle_s: float = 0.0):
         for _ in range(10):
             fn()
         torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    start.record(stream)
-    for _ in range(steps):
+    for i in range(steps):
+        ev[i].record(stream)
         fn()
-    end.record(stream)
+    ev[steps].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return start.elapsed_time(end) / steps, wall
+    per = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    mid = len(per) // 2
+    median = per[mid] if len(per) % 2 else 0.5 * (per[mid - 1] + per[mid])
+    return ev[0].elapsed_time(ev[steps]) / steps, median, wall
 
 
-def copy_rate(gib: float, steps: int, warmup: int, stream, settle_s: float = 0.0):
+def copy_rate(gib: float, steps: int, warmup: int, stream, settle_s: float = SETTLE_S):
     """Rate of a plain device-to-device copy of `gib` GiB (bytes read + written
     over the launch time)."""
     import torch
     n = int(gib * (1 << 30)) // 8
     src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    ms, _ = time_launches(lambda: dst.copy_(src), steps, warmup, stream, settle_s)
+    ms, _, _ = time_launches(lambda: dst.copy_(src), steps, warmup, stream, settle_s)
     del src, dst
     torch.cuda.empty_cache()
     return {"bytes": 2 * n * 8, "ms": ms, "GBs": 2 * n * 8 / (ms * 1e-3) / 1e9}
@@ -148,7 +156,7 @@ def bench_batch_and_rk3(sv, I, steps: int, warmup: int, stream):
                                rhs=L[off:off + sz].view(w.q.shape)))
             off += sz
         plan = sv.BatchPlan(blocks, ws[0].phys.as_tuple(), autotune=True)
-        ms_rhs, _ = time_launches(plan.execute, steps, warmup, stream, SETTLE_S)
+        ms_rhs, _, _ = time_launches(plan.execute, steps, warmup, stream)
         q0 = q_n.clone()
         bpn = BYTES_PER_NODE[tag]
         esz = 8 if tag == "f64" else 4
@@ -157,7 +165,7 @@ def bench_batch_and_rk3(sv, I, steps: int, warmup: int, stream):
             q_n.copy_(q0)
             g = sv.RK3Graph(blocks, q_n, q_1, q_2, L, 1e-3, ws[0].phys.as_tuple(), autotune=True,
                             separate_stages=separate)
-            ms_rk, _ = time_launches(g.step, steps, warmup, stream, SETTLE_S)
+            ms_rk, _, _ = time_launches(g.step, steps, warmup, stream)
             if separate:
                 # 3 x (RHS + axpby); axpby reads 3 (2 in stage 1) and writes 1 value per dof
                 rk_bytes = 3 * bpn * nodes + (4 + 4 + 3) * esz * n
@@ -187,8 +195,9 @@ def bench_adjoint(sv, I, steps: int, warmup: int, stream):
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
         q, geo, D, lam = t(src.q), t(src.geo), t(src.D), t(src.lam)
         mu = torch.empty_like(q)
-        ms, _ = time_launches(lambda: sv.volume_rhs_adjoint(q, geo, D, lam, w.phys.as_tuple(), out=mu),
-                              steps, warmup, stream, SETTLE_S)
+        ms, _, _ = time_launches(
+            lambda: sv.volume_rhs_adjoint(q, geo, D, lam, w.phys.as_tuple(), out=mu),
+            steps, warmup, stream)
         esz = 8 if tag == "f64" else 4
         out[tag] = {"ms": ms, "el_s": w.Ne / (ms * 1e-3),
                     "GBs": 25 * esz * nodes / (ms * 1e-3) / 1e9}
@@ -223,9 +232,9 @@ def bench_paper_table2(sv, I, steps: int, warmup: int, stream):
         rhs = torch.zeros_like(q)
         row = {"Ne": w.Ne, "paper_ms": PAPER_TABLE2_MS[Nq]}
         for name, dirs, geo_words in (("rs", 3, 7), ("rst", 7, 10)):
-            ms, _ = time_launches(lambda: sv.volume_rhs_ext(q, geo, D, None, None, phys, dirs=dirs,
-                                                            out=rhs, accumulate=True),
-                                  steps, warmup, stream, SETTLE_S)
+            ms, _, _ = time_launches(lambda: sv.volume_rhs_ext(q, geo, D, None, None, phys, dirs=dirs,
+                                                               out=rhs, accumulate=True),
+                                     steps, warmup, stream)
             # per node: q 8 + metric terms of the used directions and 1/J read,
             # rhs 8 read and 8 written, 4 bytes each
             byt = (8 + geo_words + 16) * 4 * nodes
@@ -263,9 +272,9 @@ def bench_ladder(sv, I, steps: int, warmup: int, stream):
     base = None
     for level in range(1, sv.LADDER_LEVELS + 1):
         n_steps = steps if level >= 3 else max(3, steps // 10)
-        ms, _ = time_launches(lambda: sv.volume_rhs_ladder(level, q, geo, D, phys, out=rhs),
-                              n_steps, min(warmup, 3) if level < 3 else warmup, stream,
-                              SETTLE_S if level >= 3 else 0.0)
+        ms, _, _ = time_launches(lambda: sv.volume_rhs_ladder(level, q, geo, D, phys, out=rhs),
+                                 n_steps, min(warmup, 3) if level < 3 else warmup, stream,
+                                 SETTLE_S if level >= 3 else 0.0)
         base = base or ms
         out["levels"][str(level)] = {"ms": ms, "speedup_vs_level1": base / ms,
                                      "GBs_final_kernel_bytes": byt / (ms * 1e-3) / 1e9}
@@ -293,10 +302,10 @@ benchmark kernel (levels 1-6) at Nq = 8 on the Table 2 shape.
         g_el = t(cast(ge))
         o1, o2 = torch.empty_like(q), torch.empty_like(q)
         ph = w.phys.as_tuple()
-        ms_node, _ = time_launches(lambda: sv.volume_rhs(q, geo, D, rr, tr, ph, out=o1),
-                                   steps, warmup, stream, SETTLE_S)
-        ms_elem, _ = time_launches(lambda: sv.volume_rhs_affine(q, g_el, D, rr, tr, ph, out=o2),
-                                   steps, warmup, stream, SETTLE_S)
+        ms_node, _, _ = time_launches(lambda: sv.volume_rhs(q, geo, D, rr, tr, ph, out=o1),
+                                      steps, warmup, stream)
+        ms_elem, _, _ = time_launches(lambda: sv.volume_rhs_affine(q, g_el, D, rr, tr, ph, out=o2),
+                                      steps, warmup, stream)
         torch.cuda.synchronize()
         diff = float(I.rel_err_per_field(o2.cpu().numpy(), o1.cpu().numpy()).max())
         esz = 8 if tag == "f64" else 4
@@ -322,9 +331,21 @@ def _cpu_model() -> str:
     return "unknown"
 
 
+def host_cores():
+    """What the host offers this process: the CPU count, the cores in its
+    affinity mask and the OpenMP thread setting."""
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"nproc": os.cpu_count(), "affinity_cores": affinity,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_baseline(w, budget_s: float):
-    """The FP64 oracle on the host cores (all of them, then one) over the same
-    N=7 workload: a reported baseline, not a target."""
+    """The FP64 oracle on the host cores (as many threads as OpenMP is given,
+    the process's share of the host; then one) over the same N=7 workload: a
+    reported baseline, not a target."""
     import oracle
     phys = w.phys.as_tuple()
     out = np.empty_like(w.q)
@@ -351,7 +372,7 @@ def cpu_baseline(w, budget_s: float):
     finally:
         oracle.set_threads(cores)
     return {"value": n * w.Ne / el, "unit": "elements/s", "cores": cores,
-            "kind": "oracle", "cpu_model": _cpu_model(),
+            "kind": "oracle", "cpu_model": _cpu_model(), "host": host_cores(),
             "value_1core": n1 * 2048 / el1,
             "sample": f"FP64 oracle over the full N=7 warped mesh ({w.Ne} elements), "
                       f"{n} passes in {el:.1f} s on {cores} threads; 1 thread: {n1} passes over "
@@ -418,9 +439,9 @@ def main(argv=None):
             *(np.asarray(x, np.float64) for x in (src.D, src.geo, src.q, src.rho_ref)),
             src.theta_ref, phys)
         err = float(I.rel_err_per_field(got, ref).max())
-        ms, wall = time_launches(fn, a.steps, a.warmup, stream)
+        ms, med, wall = time_launches(fn, a.steps, a.warmup, stream)
         bytes_launch = BYTES_PER_NODE[tag] * nodes
-        results[tag] = dict(ms=ms, wall=wall, err=err, bytes=bytes_launch,
+        results[tag] = dict(ms=ms, median_ms=med, wall=wall, err=err, bytes=bytes_launch,
                             el_s=Ne / (ms * 1e-3), gbs=bytes_launch / (ms * 1e-3) / 1e9,
                             gflops=flops_per_node(Nq) * nodes / (ms * 1e-3) / 1e9)
         print(f"# {tag}: {ms * 1e3:.1f} us/launch, {results[tag]['gbs']:.0f} GB/s, "
@@ -444,6 +465,7 @@ def main(argv=None):
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": r64["ms"],
+        "median_ms_per_step": r64["median_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -455,6 +477,7 @@ def main(argv=None):
         "gflops": r64["gflops"],
         "err_fp64": r64["err"],
         "fp32": {"value": r32["el_s"], "unit": "elements/s", "ms_per_step": r32["ms"],
+                 "median_ms_per_step": r32["median_ms"],
                  "gflops": r32["gflops"], "err_vs_fp64_oracle": r32["err"],
                  "roofline": {"bound": "hbm", "achieved": r32["gbs"], "peak": HBM_PEAK_GBS,
                               "unit": "GB/s", "frac": r32["gbs"] / HBM_PEAK_GBS,
@@ -465,7 +488,7 @@ def main(argv=None):
     }
     if not a.no_extra:
         # the same HBM moved by a plain device copy (read + write), for scale
-        c = copy_rate(2.0, 20, 5, stream, SETTLE_S)
+        c = copy_rate(2.0, 20, 5, stream)
         line["copy_reference"] = {"workload": "device-to-device copy of 2 GiB", "GBs": c["GBs"],
                                   "f64_vs_copy": r64["gbs"] / c["GBs"],
                                   "f32_vs_copy": r32["gbs"] / c["GBs"]}

@@ -110,11 +110,12 @@ const char* sem_version(void);
  * reference state, gravity and a stream).
  *   rhs = v(q)            if accumulate == 0
  *   rhs = rhs + v(q)      otherwise (the paper's rhsq update semantics)
- * rhs must not alias q, geo, D or the reference arrays.
+ * No byte of rhs may lie inside q, geo, D or the reference arrays (their
+ * extents follow from Ne, Nq and dtype).
  * Errors: Ne < 1 (the paper's assumption Ne >= 1), unsupported Nq, NULL
- * required pointer, only one of rho_ref/theta_ref, misaligned pointer,
- * unknown dtype -> SEM_ERR_INVALID_ARG / SEM_ERR_UNSUPPORTED before any HIP
- * call.  Allocates nothing and enqueues only kernel launches (no memset or
+ * required pointer, only one of rho_ref/theta_ref, misaligned pointer, rhs
+ * overlapping an input, unknown dtype -> SEM_ERR_INVALID_ARG /
+ * SEM_ERR_UNSUPPORTED before any HIP call.  Allocates nothing and enqueues only kernel launches (no memset or
  * copy), so a caller may capture it into a HIP graph.
  */
 sem_status sem_volume_rhs(int32_t Ne, int32_t Nq, sem_dtype dtype,
@@ -132,6 +133,14 @@ sem_status sem_volume_rhs_tiled(int32_t Ne, int32_t Nq, sem_dtype dtype,
                                 const void* rho_ref, const double* theta_ref,
                                 const sem_phys* phys, void* rhs, int32_t accumulate,
                                 const sem_tile* tile, void* stream);
+
+/* Caps the number of workgroups of the strided launches (the k-slice and
+ * t-column passes of sem_volume_rhs_ext and sem_volume_rhs_affine at
+ * Nq >= 12) for the whole process; 0 (the default) leaves one workgroup per
+ * tile.  A cap leaves compute units free for concurrent work and lets tests
+ * exercise the strided path at small sizes; results do not depend on it.
+ * Errors: cap < 0 -> SEM_ERR_INVALID_ARG. */
+sem_status sem_set_max_workgroups(int64_t cap);
 
 /* Writes up to `cap` compiled tile shapes for (dtype, Nq) into `out` and
  * returns how many exist (0 for an unsupported Nq or dtype). */
@@ -154,9 +163,9 @@ int32_t sem_tile_options(sem_dtype dtype, int32_t Nq, sem_tile* out, int32_t cap
  * or accumulate), then the t term added to it; the result is the same up to
  * rounding order (the t sum is added to the finished r+s value instead of
  * being summed with it before the 1/J factor).  These passes launch one
- * workgroup per tile up to a cap (2^32 work-items, or the environment
- * variable SEM_MAX_WORKGROUPS if set lower, for tests); the workgroups then
- * stride over the tiles.
+ * workgroup per tile up to a cap (2^32 work-items, or the cap set with
+ * sem_set_max_workgroups if lower); the workgroups then stride over the
+ * tiles.
  * Errors: unsupported nfields / dirs / Nq -> SEM_ERR_UNSUPPORTED; otherwise as
  * sem_volume_rhs.  Allocates nothing.
  */
@@ -219,7 +228,8 @@ sem_status sem_volume_rhs_affine(int32_t Ne, int32_t Nq, sem_dtype dtype, const 
  * (derivative of the flux column and EOS of Sec. 2):
  *   mu = (dv/dq)^T lambda        (mu += ... if accumulate != 0)
  * The reference state does not enter: d(p - p_ref)/dTheta = dp/dTheta.
- * lambda, mu: [Ne][5][Nq^3], dtype.  mu must not alias the inputs.
+ * lambda, mu: [Ne][5][Nq^3], dtype.  No byte of mu may lie inside D, geo,
+ * q or lambda.
  * Errors as for sem_volume_rhs.  Allocates nothing.
  */
 sem_status sem_volume_rhs_adjoint(int32_t Ne, int32_t Nq, sem_dtype dtype,
@@ -227,16 +237,24 @@ sem_status sem_volume_rhs_adjoint(int32_t Ne, int32_t Nq, sem_dtype dtype,
                                   const sem_phys* phys, const void* lambda, void* mu,
                                   int32_t accumulate, void* stream);
 
-/* out[i] = a*x[i] + b*(y[i] + c*z[i]) for i < n (x may be NULL when a == 0);
- * the stage update of an explicit Runge-Kutta method.  out may alias x or y.
- * Errors: n < 0, NULL required pointer, misalignment. */
+/* out[i] = a*x[i] + b*(y[i] + c*z[i]) for i < n (x may be NULL when a == 0):
+ * the stage update of an explicit Runge-Kutta method for the method-of-lines
+ * system dq/dt = v(q) + s(q) of Sec. 2 (with y the stage state, z its rate
+ * and c the time step).  out may be the same array as x, y or z; a partial
+ * overlap (same memory at a different index) is rejected.  Arrays aligned to
+ * 16 bytes run vector accesses, others a scalar path with the same results.
+ * Errors: n < 0, NULL required pointer, misalignment, partial overlap ->
+ * SEM_ERR_INVALID_ARG.  Allocates nothing. */
 sem_status sem_axpby(int64_t n, sem_dtype dtype, double a, const void* x, double b,
                      const void* y, double c, const void* z, void* out, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Mixed-order batch: many element blocks, each of one order, evaluated by ONE
- * kernel launch (one tile of elements per workgroup).  A block has the layouts above with its own Nq and
- * Ne; every block of a plan shares dtype and phys.
+ * kernel launch (one tile of elements per workgroup).  The volume term of
+ * Eq. (volterm) is local to an element (Sec. 2 evaluates it element by
+ * element, the listed kernels loop over e), so blocks of different polynomial
+ * order are independent and share one launch.  A block has the layouts above
+ * with its own Nq and Ne; every block of a plan shares dtype and phys.
  * ------------------------------------------------------------------------- */
 typedef struct sem_block {
     int32_t Nq;
@@ -289,10 +307,12 @@ sem_status sem_plan_destroy(sem_plan plan);
  * the stage update directly (the rate is never stored).  With
  * SEM_RK3_SEPARATE_STAGES each stage is a batch launch writing v into L plus
  * one sem_axpby.
- * q_n, q_1, q_2, L are flat buffers of n values of dtype; every block's q
- * must lie inside q_n and its rhs inside L at the same offset (the stage
- * plans read q_1 and q_2 at that offset).  L is written only with
- * SEM_RK3_SEPARATE_STAGES (then it holds the last stage's rate).
+ * q_n, q_1, q_2, L are distinct flat buffers of n values of dtype.  The
+ * blocks' q arrays must tile q_n[0, n) exactly (no gap, no overlap), and each
+ * block's rhs must sit in L at the offset of its q in q_n (the stage plans
+ * read q_1 and q_2 at that offset); otherwise SEM_ERR_INVALID_ARG.  L is
+ * written only with SEM_RK3_SEPARATE_STAGES (then it holds the last stage's
+ * rate).
  * flags: SEM_PLAN_AUTOTUNE / SEM_PLAN_USE_CACHE (tile shapes, chosen once and
  * shared by the three stages) and SEM_RK3_SEPARATE_STAGES.
  * ------------------------------------------------------------------------- */

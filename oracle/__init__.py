@@ -153,6 +153,18 @@ def volume_rhs_adjoint(D, geo, q, lam, phys=(1e5, 1.4, 287.0, 9.81), out=None,
     return out
 
 
+def stage_update(a, x, b, y, c, z):
+    """``a x + b (y + c z)`` in FP64: the stage update of an explicit
+    Runge-Kutta method (y the stage state, z its rate, c the time step);
+    ``x`` may be None when ``a == 0``."""
+    y = np.asarray(y, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    out = b * (y + c * z)
+    if x is not None and a != 0.0:
+        out = out + a * np.asarray(x, dtype=np.float64)
+    return out
+
+
 # Shu-Osher coefficients of the three-stage SSP Runge-Kutta scheme:
 #   q1 = q + dt L(q)
 #   q2 = 3/4 q + 1/4 (q1 + dt L(q1))
@@ -160,10 +172,14 @@ def volume_rhs_adjoint(D, geo, q, lam, phys=(1e5, 1.4, 287.0, 9.81), out=None,
 SSP_RK3 = ((0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0))
 
 
-def ssp_rk3_step(rate, q, dt):
-    """One SSP-RK3 step of ``dq/dt = rate(q)`` (explicit method of lines)."""
+def ssp_rk3_step(rate, q, dt, stage_rates=None):
+    """One SSP-RK3 step of ``dq/dt = rate(q)`` (explicit method of lines).
+    ``stage_rates``, if a list, receives the rate evaluated at each stage."""
     qn = np.asarray(q, dtype=np.float64)
     qs = qn
     for a, b in SSP_RK3:
-        qs = a * qn + b * (qs + dt * rate(qs))
+        v = rate(qs)
+        if stage_rates is not None:
+            stage_rates.append(v)
+        qs = stage_update(a, qn, b, qs, dt, v)
     return qs

@@ -7,6 +7,7 @@ HIP kernels for one MI355X (gfx950) behind a C-ABI library, ``libsem.so``.
 states; ``build`` compiles the library.
 """
 from .semvol import (  # noqa: F401
-    SemError, VolumeRHS, BatchPlan, RK3Graph, axpby, lib, tile_options, version, volume_rhs,
+    SemError, VolumeRHS, BatchPlan, RK3Graph, axpby, lib, set_max_workgroups, tile_options,
+    version, volume_rhs,
     volume_rhs_adjoint, volume_rhs_ext, volume_rhs_affine, volume_rhs_ladder, LADDER_LEVELS,
 )

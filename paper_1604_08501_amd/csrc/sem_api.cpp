@@ -4,6 +4,7 @@
 // sem_plan.cpp.  The operations themselves are documented in include/sem.h.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -139,9 +140,27 @@ sem_status check_ptr(const void* p, size_t align, const char* name, bool require
     return SEM_OK;
 }
 
+bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes)
+{
+    if (!a || !b || abytes == 0 || bbytes == 0)
+        return false;
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
+    return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+sem_status check_output_overlap(const char* out_name, const void* out, size_t out_bytes,
+                                const ByteRange* inputs, int n_inputs)
+{
+    for (int i = 0; i < n_inputs; ++i)
+        if (ranges_overlap(out, out_bytes, inputs[i].p, inputs[i].bytes))
+            return fail(SEM_ERR_INVALID_ARG, "%s [%p, +%zu B) overlaps %s [%p, +%zu B)", out_name,
+                        out, out_bytes, inputs[i].name, inputs[i].p, inputs[i].bytes);
+    return SEM_OK;
+}
+
 sem_status check_volume_ptrs(sem_dtype dt, const void* D, const void* geo, const void* q,
                              const void* rho_ref, const double* theta_ref, const sem_phys* phys,
-                             const void* rhs)
+                             const void* rhs, const VolumeExtent& x)
 {
     if (!phys)
         return fail(SEM_ERR_INVALID_ARG, "phys is NULL");
@@ -154,9 +173,17 @@ sem_status check_volume_ptrs(sem_dtype dt, const void* D, const void* geo, const
         return fail(SEM_ERR_INVALID_ARG, "rho_ref and theta_ref must both be NULL or both be given");
     SEM_TRY(check_ptr(rho_ref, es, "rho_ref", false));
     SEM_TRY(check_ptr(theta_ref, 8, "theta_ref", false));
-    if (rhs == q || rhs == geo || rhs == D || rhs == rho_ref || rhs == (const void*)theta_ref)
-        return fail(SEM_ERR_INVALID_ARG, "rhs aliases an input array");
-    return SEM_OK;
+    // rhs is written while every input is read: no byte of it may lie in an input
+    const size_t M = (size_t)x.Nq * x.Nq * x.Nq;
+    const size_t Ne = (size_t)x.Ne;
+    const ByteRange in[] = {
+        {"D", D, (size_t)x.Nq * x.Nq * es},
+        {"geo", geo, Ne * (size_t)x.geo_values_per_element * es},
+        {"q", q, Ne * (size_t)x.nf * M * es},
+        {"rho_ref", rho_ref, Ne * M * es},
+        {"theta_ref", theta_ref, Ne * M * 8},
+    };
+    return check_output_overlap("rhs", rhs, Ne * (size_t)x.nf * M * es, in, 5);
 }
 
 sem_status check_volume_args(int32_t Ne, int32_t Nq, sem_dtype dt, const void* D, const void* geo,
@@ -165,7 +192,8 @@ sem_status check_volume_args(int32_t Ne, int32_t Nq, sem_dtype dt, const void* D
 {
     SEM_TRY(check_dtype(dt));
     SEM_TRY(check_order(Ne, Nq));
-    return check_volume_ptrs(dt, D, geo, q, rho_ref, theta_ref, phys, rhs);
+    return check_volume_ptrs(dt, D, geo, q, rho_ref, theta_ref, phys, rhs,
+                             VolumeExtent{Ne, Nq, 5, 10 * (int64_t)Nq * Nq * Nq});
 }
 
 }  // namespace semapi
@@ -193,7 +221,21 @@ int tile_options(int nq, sem_tile* out, int cap)
 // ===========================================================================
 extern "C" const char* sem_last_error(void) { return last_error(); }
 
-extern "C" const char* sem_version(void) { return "semvol 0.1.0 (gfx950)"; }
+extern "C" const char* sem_version(void) { return "semvol 0.2.0 (gfx950)"; }
+
+namespace {
+std::atomic<int64_t> g_max_workgroups{0};
+}  // namespace
+
+int64_t semh::max_workgroups_cap() { return g_max_workgroups.load(std::memory_order_relaxed); }
+
+extern "C" sem_status sem_set_max_workgroups(int64_t cap)
+{
+    if (cap < 0)
+        return fail(SEM_ERR_INVALID_ARG, "cap = %lld < 0", (long long)cap);
+    g_max_workgroups.store(cap, std::memory_order_relaxed);
+    return SEM_OK;
+}
 
 extern "C" int32_t sem_tile_options(sem_dtype dtype, int32_t Nq, sem_tile* out, int32_t cap)
 {
@@ -270,7 +312,8 @@ extern "C" sem_status sem_volume_rhs_ext(int32_t Ne, int32_t Nq, sem_dtype dtype
         return fail(SEM_ERR_UNSUPPORTED,
                     "Nq = %d with %d fields and dirs = %u is not compiled for this dtype "
                     "(Nq 2..10, 12, 16)", Nq, nfields, dirs);
-    SEM_TRY(check_volume_ptrs(dtype, D, geo, q, rho_ref, theta_ref, phys, rhs));
+    SEM_TRY(check_volume_ptrs(dtype, D, geo, q, rho_ref, theta_ref, phys, rhs,
+                              VolumeExtent{Ne, Nq, nfields, 10 * (int64_t)Nq * Nq * Nq}));
     if (nfields == 5 && dirs == 7 && Nq <= kMaxNq)
         return sem_volume_rhs(Ne, Nq, dtype, D, geo, q, rho_ref, theta_ref, phys, rhs, accumulate,
                               stream);
@@ -300,7 +343,8 @@ extern "C" sem_status sem_volume_rhs_ladder(int32_t level, int32_t Ne, int32_t N
         return fail(SEM_ERR_INVALID_ARG, "Ne = %d: at least one element is required", Ne);
     if (!semh::ladder_supported(Nq) || !semh::ext_supported<float>(Nq, 8, 3))
         return fail(SEM_ERR_UNSUPPORTED, "Nq = %d is not compiled (Nq 2..10, 12, 16)", Nq);
-    SEM_TRY(check_volume_ptrs(SEM_F32, D, geo, q, nullptr, nullptr, phys, rhs));
+    SEM_TRY(check_volume_ptrs(SEM_F32, D, geo, q, nullptr, nullptr, phys, rhs,
+                              VolumeExtent{Ne, Nq, 8, 10 * (int64_t)Nq * Nq * Nq}));
     if (phys->grav != 0.0)
         return fail(SEM_ERR_UNSUPPORTED,
                     "grav = %g: the benchmark kernel has no source term (grav must be 0)", phys->grav);
@@ -331,7 +375,8 @@ extern "C" sem_status sem_volume_rhs_affine(int32_t Ne, int32_t Nq, sem_dtype dt
         return fail(SEM_ERR_UNSUPPORTED, "Nq = %d is not compiled for per-element metric terms "
                                          "in this dtype (Nq 2..10, 12, 16)",
                     Nq);
-    SEM_TRY(check_volume_ptrs(dtype, D, geo_elem, q, rho_ref, theta_ref, phys, rhs));
+    SEM_TRY(check_volume_ptrs(dtype, D, geo_elem, q, rho_ref, theta_ref, phys, rhs,
+                              VolumeExtent{Ne, Nq, 5, 10}));
     const semk::Phys ph = to_phys(phys);
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t err;
@@ -361,8 +406,16 @@ extern "C" sem_status sem_volume_rhs_adjoint(int32_t Ne, int32_t Nq, sem_dtype d
     SEM_TRY(check_ptr(q, es, "q"));
     SEM_TRY(check_ptr(lambda, es, "lambda"));
     SEM_TRY(check_ptr(mu, es, "mu"));
-    if (mu == q || mu == geo || mu == D || mu == lambda)
-        return fail(SEM_ERR_INVALID_ARG, "mu aliases an input array");
+    {
+        const size_t M = (size_t)Nq * Nq * Nq;
+        const ByteRange in[] = {
+            {"D", D, (size_t)Nq * Nq * es},
+            {"geo", geo, (size_t)Ne * 10 * M * es},
+            {"q", q, (size_t)Ne * 5 * M * es},
+            {"lambda", lambda, (size_t)Ne * 5 * M * es},
+        };
+        SEM_TRY(check_output_overlap("mu", mu, (size_t)Ne * 5 * M * es, in, 4));
+    }
     const int epb = default_epb(Nq);
     const semk::Phys ph = to_phys(phys);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -397,6 +450,15 @@ extern "C" sem_status sem_axpby(int64_t n, sem_dtype dtype, double a, const void
     SEM_TRY(check_ptr(y, es, "y"));
     SEM_TRY(check_ptr(z, es, "z"));
     SEM_TRY(check_ptr(out, es, "out"));
+    // each value is read and written by one thread, so out may coincide with
+    // an input; a shifted overlap would race
+    {
+        const size_t bytes = (size_t)n * es;
+        const ByteRange in[] = {{"x", a != 0.0 ? x : nullptr, bytes}, {"y", y, bytes}, {"z", z, bytes}};
+        for (const ByteRange& r : in)
+            if (r.p != out)
+                SEM_TRY(check_output_overlap("out", out, bytes, &r, 1));
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t err;
     if (dtype == SEM_F64)

@@ -38,10 +38,32 @@ DefaultTile default_tile(sem_dtype dt, int nq);
 sem_status check_dtype(sem_dtype dt);
 sem_status check_order(int32_t Ne, int32_t Nq);
 sem_status check_ptr(const void* p, size_t align, const char* name, bool required = true);
-// Pointers, alignment, the reference pair and aliasing of a volume-term call.
+// A named device array and its extent in bytes (for overlap checks).
+struct ByteRange {
+    const char* name;
+    const void* p;
+    size_t bytes;
+};
+// True when the byte ranges [a, a + abytes) and [b, b + bbytes) intersect
+// (NULL or empty ranges never do).
+bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes);
+// SEM_ERR_INVALID_ARG when the output range overlaps any input range.
+sem_status check_output_overlap(const char* out_name, const void* out, size_t out_bytes,
+                                const ByteRange* inputs, int n_inputs);
+
+// Sizes of the arrays of a volume-term call: Ne elements of Nq^3 nodes, nf
+// fields, geo_values_per_element metric values (10 Nq^3 per node, 10 for the
+// per-element form).
+struct VolumeExtent {
+    int64_t Ne;
+    int Nq;
+    int nf;
+    int64_t geo_values_per_element;
+};
+// Pointers, alignment, the reference pair, and rhs overlapping an input.
 sem_status check_volume_ptrs(sem_dtype dt, const void* D, const void* geo, const void* q,
                              const void* rho_ref, const double* theta_ref, const sem_phys* phys,
-                             const void* rhs);
+                             const void* rhs, const VolumeExtent& x);
 sem_status check_volume_args(int32_t Ne, int32_t Nq, sem_dtype dt, const void* D, const void* geo,
                              const void* q, const void* rho_ref, const double* theta_ref,
                              const sem_phys* phys, const void* rhs);

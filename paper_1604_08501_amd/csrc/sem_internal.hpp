@@ -70,6 +70,10 @@ template <typename T>
 hipError_t launch_volume_affine(int nq, const semk::BlockPtrs<T>& B, const semk::Phys& ph,
                                 int accumulate, hipStream_t s);
 
+// Workgroup cap of the strided k-slice and t-column launches set by
+// sem_set_max_workgroups (0 = none); one relaxed atomic load.
+int64_t max_workgroups_cap();
+
 // Optimisation ladder of the fused r+s, 8-field FP32 kernel (ladder.hip):
 // levels 1..5, Nq 2..10, 12, 16.
 bool ladder_supported(int nq);

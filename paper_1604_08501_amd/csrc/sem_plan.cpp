@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -726,6 +727,40 @@ extern "C" sem_status sem_rk3_graph_create(const sem_block* blocks, int32_t nblo
     const char* lb = static_cast<const char*>(L);
     for (int k = 0; k < 3; ++k)
         sb[k].assign(blocks, blocks + nblocks);
+    {
+        // the four buffers are distinct: each stage reads one and writes another
+        const size_t nb = (size_t)n * es;
+        const ByteRange bufs[] = {{"q_n", q_n, nb}, {"q_1", q_1, nb}, {"q_2", q_2, nb}, {"L", L, nb}};
+        for (int i = 0; i < 4; ++i)
+            SEM_TRY(check_output_overlap(bufs[i].name, bufs[i].p, nb, bufs + i + 1, 3 - i));
+    }
+    // the blocks' q arrays tile q_n[0, n) exactly, so that both stage modes
+    // advance every value of q_n (and no value twice)
+    {
+        std::vector<std::pair<int64_t, int64_t>> spans;   // byte offset, length
+        for (int i = 0; i < nblocks; ++i) {
+            if (blocks[i].Ne < 1 || blocks[i].Nq < kMinNq || blocks[i].Nq > kMaxNq)
+                return fail(SEM_ERR_INVALID_ARG, "block %d: Ne = %d, Nq = %d", i, blocks[i].Ne,
+                            blocks[i].Nq);
+            const int64_t m = (int64_t)blocks[i].Nq * blocks[i].Nq * blocks[i].Nq;
+            spans.emplace_back(static_cast<const char*>(blocks[i].q) - static_cast<const char*>(q_n),
+                               (int64_t)blocks[i].Ne * 5 * m * (int64_t)es);
+        }
+        std::sort(spans.begin(), spans.end());
+        int64_t end = 0;
+        for (const auto& sp : spans) {
+            if (sp.first != end)
+                return fail(SEM_ERR_INVALID_ARG,
+                            "the blocks' q arrays must tile q_n[0, n) exactly: %s at byte %lld "
+                            "(expected a block starting at byte %lld)",
+                            sp.first < end ? "overlap" : "gap", (long long)sp.first, (long long)end);
+            end += sp.second;
+        }
+        if (end != n * (int64_t)es)
+            return fail(SEM_ERR_INVALID_ARG,
+                        "the blocks' q arrays cover %lld of the %lld bytes of q_n[0, n)",
+                        (long long)end, (long long)(n * (int64_t)es));
+    }
     for (int i = 0; i < nblocks; ++i) {
         const int64_t m = (int64_t)blocks[i].Nq * blocks[i].Nq * blocks[i].Nq;
         const int64_t bytes = (int64_t)blocks[i].Ne * 5 * m * (int64_t)es;

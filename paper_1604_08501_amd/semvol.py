@@ -35,7 +35,7 @@ EXPORTS = (
     "sem_volume_rhs_ext", "sem_volume_rhs_ladder", "sem_volume_rhs_affine", "sem_volume_rhs_adjoint",
     "sem_axpby", "sem_batch_plan", "sem_batch_execute",
     "sem_plan_describe", "sem_plan_destroy", "sem_rk3_graph_create", "sem_rk3_graph_launch",
-    "sem_rk3_graph_describe", "sem_rk3_graph_destroy",
+    "sem_rk3_graph_describe", "sem_rk3_graph_destroy", "sem_set_max_workgroups",
 )
 
 
@@ -96,6 +96,7 @@ def lib() -> ctypes.CDLL:
         "sem_rk3_graph_launch": ([vp, vp], i32),
         "sem_rk3_graph_describe": ([vp, ctypes.c_char_p, i32], i32),
         "sem_rk3_graph_destroy": ([vp], i32),
+        "sem_set_max_workgroups": ([i64], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -112,6 +113,12 @@ def _check(status: int) -> None:
 
 def version() -> str:
     return lib().sem_version().decode()
+
+
+def set_max_workgroups(cap: int) -> None:
+    """Process-wide cap on the workgroups of the strided (k-slice and
+    t-column) launches; 0 restores one workgroup per tile."""
+    _check(lib().sem_set_max_workgroups(int(cap)))
 
 
 def tile_options(dtype: torch.dtype, Nq: int):

@@ -341,6 +341,44 @@ def test_ssp_rk3_third_order(oracle_mod):
     assert np.all(rates > 2.8), rates
 
 
+def test_stage_update_is_the_runge_kutta_combination(oracle_mod):
+    x, y, z = np.array([2.0, -1.0]), np.array([0.5, 4.0]), np.array([3.0, -8.0])
+    np.testing.assert_array_equal(oracle_mod.stage_update(0.75, x, 0.25, y, 0.5, z),
+                                  [0.75 * 2.0 + 0.25 * (0.5 + 1.5), 0.75 * -1.0 + 0.25 * (4.0 - 4.0)])
+    np.testing.assert_array_equal(oracle_mod.stage_update(0.0, None, 1.0, y, 2.0, z), y + 2.0 * z)
+
+
+def test_rk3_storage_rounding_bound(oracle_mod):
+    """Storing the SSP-RK3 stage values in FP32 (as the FP32 form does) changes
+    the increment q_new - q by no more than a first-order bound: the rounding
+    of values of size max|q| (eps max|q|, once for the stored q_new and once
+    for each stage value the next rate reads, weighted 1/4 and 2/3), plus, in
+    the momentum rates, the pressure change gamma p eps/2 of a rounded Theta
+    amplified by 3 sum_n |D_in| max|g| max(1/J) and scaled by dt.  The GPU
+    tests gate the RK3 step with the oracle's own rounded-stage step; this
+    pins that emulation to the bound."""
+    dt = 1e-3
+    eps = 2.0 ** -23
+    rnd = lambda a: np.asarray(a, np.float32).astype(np.float64)
+    mx = lambda a: np.abs(a).transpose(1, 0, 2).reshape(5, -1).max(axis=1)
+    for w in I.mixed_order_workloads(orders=(1, 3, 5, 7, 9), per_order=12, k=86):
+        src = I.upcast(I.to_fp32(w))
+        rate = lambda qq: oracle_mod.volume_rhs(src.D, src.geo, qq, src.rho_ref, src.theta_ref,
+                                                src.phys.as_tuple())
+        exact = oracle_mod.ssp_rk3_step(rate, src.q, dt)
+        qs = src.q
+        for a, b in oracle_mod.SSP_RK3:
+            qs = rnd(oracle_mod.stage_update(a, src.q, b, qs, dt, rate(qs)))
+        dq = mx(exact - src.q)
+        p_max = np.max(src.phys.p0 * (src.phys.R * src.q[:, 4] / src.phys.p0) ** src.phys.gamma)
+        amp = 3 * np.abs(src.D).sum(axis=1).max() * np.abs(src.geo[:, :9]).max() * src.geo[:, 9].max()
+        bound = 2.0 * eps * mx(src.q) / dq
+        bound[1:4] += dt * src.phys.gamma * p_max * 0.5 * eps * amp / dq[1:4]
+        e = I.rel_err_per_field(qs - src.q, exact - src.q)
+        assert np.all(e <= bound), (w.N, e, bound)
+        assert np.all(e > 0)            # the emulation does round
+
+
 # ---------------------------------------------------------------------------
 # Passive tracers and the reference-direction subset (the paper's benchmark
 # kernel: 8 fields, r and s terms only)
