@@ -321,6 +321,53 @@ benchmark kernel (levels 1-6) at Nq = 8 on the Table 2 shape.
     return out
 
 
+def surface_bytes_per_element(Nq: int, esz: int) -> int:
+    """Algorithmic bytes of the surface term per element (accumulating into
+    rhs): at each of the Nb = Nq^3 - (Nq-2)^3 boundary nodes the state (5),
+    1/J and rhs read and written (10) in the working precision and Theta_ref
+    (8 B); at each of the 6 Nq^2 face-node pairs the three metric terms of the
+    face direction; the six neighbour indices.  The neighbour's face values
+    are its own boundary values, moved once."""
+    nb = Nq ** 3 - max(Nq - 2, 0) ** 3
+    return (16 * esz + 8) * nb + 3 * esz * 6 * Nq * Nq + 24
+
+
+def bench_surface(sv, I, w, steps: int, warmup: int, stream):
+    """Surface term (strong-form DG face term, local Lax-Friedrichs flux) at
+    N=7 on the periodic warped 32^3 box, accumulated into rhs; and the whole
+    rate v + s (the volume launch, then the surface launch)."""
+    import torch
+    Ne, Nq = w.Ne, w.Nq
+    out = {"workload": "surface term, N=7, 32768 warped elements, periodic, rhs += s",
+           "bytes_per_element": {}}
+    for tag, dt in (("f64", torch.float64), ("f32", torch.float32)):
+        src = w if dt == torch.float64 else I.to_fp32(w)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        q, geo, D, rr, tr, nbr = (t(src.q), t(src.geo), t(src.D), t(src.rho_ref),
+                                  t(src.theta_ref), t(w.nbr))
+        rhs = torch.zeros_like(q)
+        ph = w.phys.as_tuple()
+        ms, med, _ = time_launches(lambda: sv.surface_rhs(q, geo, nbr, tr, ph, out=rhs,
+                                                          accumulate=True), steps, warmup, stream)
+
+        def full():
+            sv.volume_rhs(q, geo, D, rr, tr, ph, out=rhs)
+            sv.surface_rhs(q, geo, nbr, tr, ph, out=rhs, accumulate=True)
+        ms_full, _, _ = time_launches(full, steps, warmup, stream)
+        esz = 8 if tag == "f64" else 4
+        bpe = surface_bytes_per_element(Nq, esz)
+        gbs = bpe * Ne / (ms * 1e-3) / 1e9
+        out["bytes_per_element"][tag] = bpe
+        out[tag] = {"ms": ms, "median_ms": med, "el_s": Ne / (ms * 1e-3), "GBs": gbs,
+                    "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
+                                 "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS},
+                    "volume_plus_surface_ms": ms_full,
+                    "volume_plus_surface_el_s": Ne / (ms_full * 1e-3)}
+        del q, geo, D, rr, tr, nbr, rhs
+        torch.cuda.empty_cache()
+    return out
+
+
 def _cpu_model() -> str:
     try:
         for line in open("/proc/cpuinfo"):
@@ -492,6 +539,7 @@ def main(argv=None):
         line["copy_reference"] = {"workload": "device-to-device copy of 2 GiB", "GBs": c["GBs"],
                                   "f64_vs_copy": r64["gbs"] / c["GBs"],
                                   "f32_vs_copy": r32["gbs"] / c["GBs"]}
+        line["surface"] = bench_surface(sv, I, w, a.steps, a.warmup, stream)
         line["batch_mixed_order"] = bench_batch_and_rk3(sv, I, a.steps, a.warmup, stream)
         line["adjoint"] = bench_adjoint(sv, I, a.steps, a.warmup, stream)
         line["paper_table2"] = bench_paper_table2(sv, I, a.steps, a.warmup, stream)

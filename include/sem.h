@@ -237,6 +237,44 @@ sem_status sem_volume_rhs_adjoint(int32_t Ne, int32_t Nq, sem_dtype dtype,
                                   const sem_phys* phys, const void* lambda, void* mu,
                                   int32_t accumulate, void* stream);
 
+/*
+ * Surface term s of the method-of-lines rate dq/dt = v(q) + s(q) (Sec. 2
+ * splits the rate into a volume and a surface contribution and defines only
+ * the volume one).  Reading taken: the strong-form discontinuous Galerkin face
+ * term on the same GLL nodes, with a local Lax-Friedrichs (Rusanov) flux.  At
+ * a node x of face (d, side) of element e, with N = sigma (g_0d, g_1d,
+ * g_2d)(x) (sigma = -1 on the face xi_d = -1, +1 on xi_d = +1), q- the state
+ * of e at x and q+ the neighbour's state at the same node:
+ *   s_b(x) += -(1/J(x)) (N(N+1)/2) [ (Fn_b(q+) - Fn_b(q-)) / 2
+ *                                     - lambda |N| (q+_b - q-_b) / 2 ]
+ * Fn(q) = sum_a N_a f_a(q) is the flux column of set 2C with the volume term's
+ * pressure (each side's p - p_ref when theta_ref is given, else p),
+ * lambda = max over both sides of |u . N|/|N| + sqrt(gamma p / rho) (full p),
+ * and N(N+1)/2 = 1/w_N, the inverse GLL weight of the end nodes.  Nodes on
+ * edges and corners collect the terms of each of their faces.
+ *   nbr        [Ne][6] int32: the element across faces r-, r+, s-, s+, t-, t+
+ *              (face 2 d + side).  Meshes are conforming with aligned
+ *              faces: across its r = -1 face, node (0, j, k) of e meets node
+ *              (N, j, k) of nbr[e][0] (likewise for s and t).  An index
+ *              outside [0, Ne) is a boundary face whose exterior state equals
+ *              the interior one, so it adds nothing; the kernel never reads
+ *              through such an index.
+ *   geo, q     as for sem_volume_rhs (only face nodes are read)
+ *   theta_ref  [Ne][Nq^3] FP64 or NULL: the reference of the pressure
+ *              perturbation (where it is continuous across a face it cancels;
+ *              in FP32 it keeps the pressure difference accurate)
+ *   rhs        rhs = s (zero at interior nodes) if accumulate == 0, else
+ *              rhs += s (after sem_volume_rhs this completes v + s)
+ *   Nq         2..10, 12, 16
+ * No byte of rhs may lie inside nbr, geo, q or theta_ref.
+ * Errors: Ne < 1, NULL or misaligned pointer, rhs overlapping an input,
+ * unknown dtype -> SEM_ERR_INVALID_ARG; unsupported Nq -> SEM_ERR_UNSUPPORTED.
+ * Allocates nothing; enqueues one kernel launch.
+ */
+sem_status sem_surface_rhs(int32_t Ne, int32_t Nq, sem_dtype dtype, const int32_t* nbr,
+                           const void* geo, const void* q, const double* theta_ref,
+                           const sem_phys* phys, void* rhs, int32_t accumulate, void* stream);
+
 /* out[i] = a*x[i] + b*(y[i] + c*z[i]) for i < n (x may be NULL when a == 0):
  * the stage update of an explicit Runge-Kutta method for the method-of-lines
  * system dq/dt = v(q) + s(q) of Sec. 2 (with y the stage state, z its rate

@@ -9,6 +9,9 @@ or calls anything here, and nothing here imports the product package.
 * :func:`volume_rhs` / :func:`volume_rhs_adjoint` call the plain FP64 C
   loops in ``sem_oracle.c`` (built with ``gcc -O2 -ffp-contract=off
   -fopenmp``, no fast-math);
+* :func:`surface_rhs` calls the plain FP64 C loops of the surface term
+  (strong-form discontinuous Galerkin face term with a local Lax-Friedrichs
+  flux, the reading taken for the s of dq/dt = v + s in Sec. 2);
 * :func:`ssp_rk3_step` composes any rate function into one step of the
   three-stage strong-stability-preserving Runge-Kutta scheme (Shu-Osher
   form), used for the method-of-lines time step of Sec. 2.
@@ -60,6 +63,8 @@ def _load():
     lib.sem_oracle_volume_rhs_ext.restype = None
     lib.sem_oracle_volume_rhs_adjoint.argtypes = [i64, i64, i32, p, p, p, d, d, d, d, p, p, i32]
     lib.sem_oracle_volume_rhs_adjoint.restype = None
+    lib.sem_oracle_surface_rhs.argtypes = [i64, i64, i64, i32, p, p, p, p, d, d, d, p, i32]
+    lib.sem_oracle_surface_rhs.restype = None
     lib.sem_oracle_max_threads.restype = ctypes.c_int
     lib.sem_oracle_set_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -150,6 +155,30 @@ def volume_rhs_adjoint(D, geo, q, lam, phys=(1e5, 1.4, 287.0, 9.81), out=None,
     p0, gamma, R, grav = phys
     lib.sem_oracle_volume_rhs_adjoint(e0, e1, Nq, _ptr(D), _ptr(geo), _ptr(q), p0, gamma, R,
                                       grav, _ptr(lam), _ptr(out), int(bool(accumulate)))
+    return out
+
+
+def surface_rhs(geo, q, nbr, theta_ref=None, phys=(1e5, 1.4, 287.0, 9.81), out=None,
+                accumulate=False, elements=None):
+    """Surface term s of ``dq/dt = v + s`` in FP64 (see ``sem_oracle_surface_rhs``
+    in ``sem_oracle.c``): ``nbr`` is ``[Ne, 6]`` int32, the element across
+    faces r-, r+, s-, s+, t-, t+; an index outside ``[0, Ne)`` is a boundary
+    face that adds nothing.  With ``theta_ref`` the pressure in the fluxes is
+    each side's perturbation about its own reference value."""
+    lib = _load()
+    geo, q, theta_ref = _f64(geo), _f64(q), _f64(theta_ref)
+    nbr = np.ascontiguousarray(nbr, dtype=np.int32)
+    Ne, nf, M = q.shape
+    Nq = round(M ** (1.0 / 3.0))
+    assert nf == 5 and Nq ** 3 == M and geo.shape == (Ne, 10, M) and nbr.shape == (Ne, 6)
+    assert theta_ref is None or theta_ref.shape == (Ne, M)
+    if out is None:
+        out = np.zeros_like(q)
+    assert out.dtype == np.float64 and out.flags.c_contiguous and out.shape == q.shape
+    e0, e1 = (0, Ne) if elements is None else elements
+    p0, gamma, R, _grav = phys
+    lib.sem_oracle_surface_rhs(e0, e1, Ne, Nq, _ptr(nbr), _ptr(geo), _ptr(q), _ptr(theta_ref),
+                               p0, gamma, R, _ptr(out), int(bool(accumulate)))
     return out
 
 

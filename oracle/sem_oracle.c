@@ -30,7 +30,11 @@
  *   - gravity (left out by the paper) enters as the source -grav*(rho-rho_ref)
  *     on U3 only, with x_3 vertical;
  *   - with a reference state the pressure in the flux is the perturbation
- *     p - p_ref, p_ref = EOS(Theta_ref); without one it is the full p.
+ *     p - p_ref, p_ref = EOS(Theta_ref); without one it is the full p;
+ *   - the surface term s of dq/dt = v + s (Sec. 2 names it, the paper does
+ *     not define it) is the strong-form discontinuous Galerkin face term on
+ *     the same GLL nodes with a local Lax-Friedrichs (Rusanov) numerical flux;
+ *     see sem_oracle_surface_rhs.
  */
 #include <math.h>
 #include <stdint.h>
@@ -273,5 +277,119 @@ void sem_oracle_volume_rhs_adjoint(int64_t e0, int64_t e1, int32_t Nq, const dou
         }
         free(w);
         free(G);
+    }
+}
+
+/*
+ * Surface term s of the method-of-lines rate dq/dt = v(q) + s(q) (Sec. 2),
+ * read as the strong-form discontinuous Galerkin face term on the GLL nodes
+ * of the volume term (collocated quadrature), with a local Lax-Friedrichs
+ * (Rusanov) numerical flux.
+ *
+ * Faces of element e: f = 2 d + side, d = 0, 1, 2 the reference direction
+ * (r, s, t) and side 0 the face xi_d = -1, side 1 the face xi_d = +1.
+ * nbr[e][f] is the element across face f.  Neighbours are conforming and
+ * aligned: the neighbour's matching face is its face 2 d + (1 - side), and a
+ * face node keeps its two tangential indices across the face (node
+ * (0, j, k) of e meets node (N, j, k) of the element across its r = -1 face).
+ * A neighbour index outside [0, Ne) marks a boundary face whose exterior
+ * state equals the interior one, so that face adds nothing.
+ *
+ * At a node x of face (d, side), with sigma = -1 (side 0) or +1 (side 1):
+ *   N      = sigma (g_0d, g_1d, g_2d)(x)      outward normal times area factor
+ *   q-, q+ = the state of e at x, of the neighbour at its node of x
+ *   p-, p+ = EOS pressure of q-, q+ (full pressure, for the sound speed)
+ *   p'-, p'+ = the pressure in the flux: p- - p_ref-, p+ - p_ref+ with each
+ *            side's own reference value (the volume term's pressure), or the
+ *            full pressures when no reference state is given
+ *   Fn(q, p') = sum_a N_a f_a(q, p')          normal flux
+ *   c      = sqrt(gamma p / rho),  lambda = max(|u- . n| + c-, |u+ . n| + c+),
+ *            n = N / |N|
+ *   F*     = (Fn(q-, p'-) + Fn(q+, p'+)) / 2 - lambda |N| (q+ - q-) / 2
+ *   s_b(x) += -(1/J(x)) / w_N * (F*_b - Fn_b(q-, p'-)),
+ * w_N = 2 / (N (N + 1)) the GLL weight of the end nodes.  Nodes on an edge or
+ * a corner collect the terms of each of their faces.  Where the reference
+ * state is continuous across a face, p_ref cancels between F* and Fn(q-) and
+ * s is the same with or without it; taking each side's own reference keeps
+ * the two elements' numerical fluxes opposite where it is not (the z-periodic
+ * faces of a stratified box), so that v + s stays conservative.
+ *
+ * Elements [e0, e1) are evaluated (rhs indexed like q); Ne bounds the
+ * neighbour indices.  theta_ref [Ne][Nq^3] or NULL.  accumulate != 0 adds s to
+ * rhs, else rhs = s (zero at interior nodes).
+ */
+void sem_oracle_surface_rhs(int64_t e0, int64_t e1, int64_t Ne, int32_t Nq, const int32_t* nbr,
+                            const double* geo, const double* q, const double* theta_ref,
+                            double p0, double gamma, double R, double* rhs, int32_t accumulate)
+{
+    const int64_t M = (int64_t)Nq * Nq * Nq;
+    const int N = Nq - 1;
+    const double wN = 2.0 / ((double)N * (N + 1));
+    const int64_t stride[3] = {1, Nq, (int64_t)Nq * Nq};
+#pragma omp parallel
+    {
+        double* sacc = (double*)malloc(sizeof(double) * (size_t)M * 5);
+#pragma omp for schedule(static)
+        for (int64_t e = e0; e < e1; ++e) {
+            const double* qe = q + e * 5 * M;
+            const double* ge = geo + e * 10 * M;
+            memset(sacc, 0, sizeof(double) * (size_t)M * 5);
+            for (int f = 0; f < 6; ++f) {
+                const int d = f / 2, side = f % 2;
+                const double sigma = side ? 1.0 : -1.0;
+                const int64_t en = nbr[e * 6 + f];
+                const int boundary = en < 0 || en >= Ne;
+                /* the two tangential directions of the face */
+                const int da = d == 0 ? 1 : 0, db = d == 2 ? 1 : 2;
+                for (int b2 = 0; b2 < Nq; ++b2)
+                    for (int a2 = 0; a2 < Nq; ++a2) {
+                        const int64_t m = (side ? N : 0) * stride[d] + a2 * stride[da] +
+                                          b2 * stride[db];
+                        const int64_t mp = (side ? 0 : N) * stride[d] + a2 * stride[da] +
+                                           b2 * stride[db];
+                        double qm[5], qp[5];
+                        for (int c = 0; c < 5; ++c) {
+                            qm[c] = qe[c * M + m];
+                            qp[c] = boundary ? qm[c] : q[en * 5 * M + c * M + mp];
+                        }
+                        double prm = 0.0, prp = 0.0;   /* reference pressures */
+                        if (theta_ref) {
+                            prm = eos_pressure(theta_ref[e * M + m], p0, gamma, R);
+                            prp = boundary ? prm
+                                           : eos_pressure(theta_ref[en * M + mp], p0, gamma, R);
+                        }
+                        double Nv[3], nn = 0.0;
+                        for (int a = 0; a < 3; ++a) {
+                            Nv[a] = sigma * ge[(3 * d + a) * M + m];
+                            nn += Nv[a] * Nv[a];
+                        }
+                        nn = sqrt(nn);
+                        const double pm = eos_pressure(qm[4], p0, gamma, R);
+                        const double pp = eos_pressure(qp[4], p0, gamma, R);
+                        double fm[3][MAXF], fp[3][MAXF];
+                        physical_flux(qm, 5, pm - prm, fm);
+                        physical_flux(qp, 5, pp - prp, fp);
+                        const double unm = (Nv[0] * qm[1] + Nv[1] * qm[2] + Nv[2] * qm[3]) / (qm[0] * nn);
+                        const double unp = (Nv[0] * qp[1] + Nv[1] * qp[2] + Nv[2] * qp[3]) / (qp[0] * nn);
+                        const double lm = fabs(unm) + sqrt(gamma * pm / qm[0]);
+                        const double lp = fabs(unp) + sqrt(gamma * pp / qp[0]);
+                        const double lambda = lm > lp ? lm : lp;
+                        const double jinv = ge[9 * M + m];
+                        for (int c = 0; c < 5; ++c) {
+                            double Fm = 0.0, Fp = 0.0;
+                            for (int a = 0; a < 3; ++a) {
+                                Fm += Nv[a] * fm[a][c];
+                                Fp += Nv[a] * fp[a][c];
+                            }
+                            const double Fstar = 0.5 * (Fm + Fp) - 0.5 * lambda * nn * (qp[c] - qm[c]);
+                            sacc[c * M + m] += -(jinv / wN) * (Fstar - Fm);
+                        }
+                    }
+            }
+            double* re = rhs + e * 5 * M;
+            for (int64_t x = 0; x < 5 * M; ++x)
+                re[x] = accumulate ? re[x] + sacc[x] : sacc[x];
+        }
+        free(sacc);
     }
 }

@@ -439,6 +439,57 @@ extern "C" sem_status sem_volume_rhs_adjoint(int32_t Ne, int32_t Nq, sem_dtype d
     return SEM_OK;
 }
 
+extern "C" sem_status sem_surface_rhs(int32_t Ne, int32_t Nq, sem_dtype dtype, const int32_t* nbr,
+                                      const void* geo, const void* q, const double* theta_ref,
+                                      const sem_phys* phys, void* rhs, int32_t accumulate,
+                                      void* stream)
+{
+    SEM_TRY(check_dtype(dtype));
+    if (Ne < 1)
+        return fail(SEM_ERR_INVALID_ARG, "Ne = %d: at least one element is required", Ne);
+    const bool ok = dtype == SEM_F64 ? semh::surface_supported<double>(Nq)
+                                     : semh::surface_supported<float>(Nq);
+    if (!ok)
+        return fail(SEM_ERR_UNSUPPORTED, "Nq = %d is not compiled for the surface term "
+                                         "(Nq 2..10, 12, 16)", Nq);
+    if (!phys)
+        return fail(SEM_ERR_INVALID_ARG, "phys is NULL");
+    const size_t es = elem_size(dtype);
+    SEM_TRY(check_ptr(nbr, 4, "nbr"));
+    SEM_TRY(check_ptr(geo, es, "geo"));
+    SEM_TRY(check_ptr(q, es, "q"));
+    SEM_TRY(check_ptr(theta_ref, 8, "theta_ref", false));
+    SEM_TRY(check_ptr(rhs, es, "rhs"));
+    {
+        const size_t M = (size_t)Nq * Nq * Nq;
+        const ByteRange in[] = {
+            {"nbr", nbr, (size_t)Ne * 6 * 4},
+            {"geo", geo, (size_t)Ne * 10 * M * es},
+            {"q", q, (size_t)Ne * 5 * M * es},
+            {"theta_ref", theta_ref, (size_t)Ne * M * 8},
+        };
+        SEM_TRY(check_output_overlap("rhs", rhs, (size_t)Ne * 5 * M * es, in, 4));
+    }
+    const semk::Phys ph = to_phys(phys);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t err;
+    if (dtype == SEM_F64)
+        err = semh::launch_surface<double>(
+            Nq, semk::SurfPtrs<double>{nbr, static_cast<const double*>(geo),
+                                       static_cast<const double*>(q), theta_ref,
+                                       static_cast<double*>(rhs), Ne},
+            ph, accumulate, s);
+    else
+        err = semh::launch_surface<float>(
+            Nq, semk::SurfPtrs<float>{nbr, static_cast<const float*>(geo),
+                                      static_cast<const float*>(q), theta_ref,
+                                      static_cast<float*>(rhs), Ne},
+            ph, accumulate, s);
+    if (err != hipSuccess)
+        return hip_fail(err, "surface kernel launch");
+    return SEM_OK;
+}
+
 extern "C" sem_status sem_axpby(int64_t n, sem_dtype dtype, double a, const void* x, double b,
                                 const void* y, double c, const void* z, void* out, void* stream)
 {

@@ -41,6 +41,17 @@ struct BlockPtrs {
     const T* rk_x;           // fused Runge-Kutta stage only: x of out = a x + b (q + dt v)
 };
 
+// Arrays of the surface term (face term of dq/dt = v + s).
+template <typename T>
+struct SurfPtrs {
+    const int32_t* nbr;         // [Ne][6] element across faces r-, r+, s-, s+, t-, t+
+    const T* geo;               // [Ne][10][M]
+    const T* q;                 // [Ne][5][M]
+    const double* theta_ref;    // [Ne][M] or null
+    T* rhs;                     // [Ne][5][M]
+    int64_t Ne;
+};
+
 // Stage update of an explicit Runge-Kutta method fused into the epilogue of
 // the volume term: out = a*x + b*(q + dt*v(q)), x not read when a == 0.
 struct RkStage {

@@ -70,6 +70,13 @@ template <typename T>
 hipError_t launch_volume_affine(int nq, const semk::BlockPtrs<T>& B, const semk::Phys& ph,
                                 int accumulate, hipStream_t s);
 
+// Surface term (surface_*.hip): Nq 2..10, 12, 16.
+template <typename T>
+bool surface_supported(int nq);
+template <typename T>
+hipError_t launch_surface(int nq, const semk::SurfPtrs<T>& B, const semk::Phys& ph, int accumulate,
+                          hipStream_t s);
+
 // Workgroup cap of the strided k-slice and t-column launches set by
 // sem_set_max_workgroups (0 = none); one relaxed atomic load.
 int64_t max_workgroups_cap();
@@ -103,6 +110,7 @@ hipError_t launch_batch(int nt, const Tile* d_tiles, int ntiles,
                         hipStream_t s);
 template <typename T>
 hipError_t batch_blocks_per_cu(int nt, int lds_bytes, bool rk, int* out);
+
 // Must run once per process before occupancy queries or launches (sets the
 // dynamic-LDS limit of the batch kernels).
 template <typename T>

@@ -498,29 +498,34 @@ sem_status autotune(PlanCore& p, bool use_cache, hipStream_t s)
     return SEM_OK;
 }
 
+// The built-in shape of one order in a launch of nt threads: the
+// single-order default tile, else the historical small shape with all fluxes
+// resident, else the same count aliased.  False if none fits.
+bool default_shape(sem_dtype dt, int nt, int nq, bool rk, int* epb, int* lay)
+{
+    const DefaultTile dft = default_tile(dt, nq);
+    if (variant_ok(dt, nt, nq, dft.epb, dft.lay, rk)) {
+        *epb = dft.epb;
+        *lay = dft.lay;
+        return true;
+    }
+    *epb = default_epb(nq);
+    for (int l : {(int)semk::FULL, (int)semk::ALIAS})
+        if (variant_ok(dt, nt, nq, *epb, l, rk)) {
+            *lay = l;
+            return true;
+        }
+    return false;
+}
+
 // Built-in batch shapes (no autotuning): the smallest workgroup size among
-// 256, 512 and 1024 for which every order has its single-order default tile
-// (all fluxes in LDS, else one direction at a time).
+// 256, 512 and 1024 for which every order has a built-in shape.
 sem_status default_shapes(PlanCore& p)
 {
     for (int nt : semh::kBatchThreads) {
         bool all = true;
-        for (OrderChoice& o : p.orders) {
-            // the single-order default shape, else the historical small
-            // shapes with all fluxes resident, else aliased
-            const DefaultTile dft = default_tile(p.dtype, o.nq);
-            o.epb = dft.epb;
-            o.lay = dft.lay;
-            if (variant_ok(p.dtype, nt, o.nq, o.epb, o.lay, p.rk))
-                continue;
-            o.epb = default_epb(o.nq);
-            if (variant_ok(p.dtype, nt, o.nq, o.epb, semk::FULL, p.rk))
-                o.lay = semk::FULL;
-            else if (variant_ok(p.dtype, nt, o.nq, o.epb, semk::ALIAS, p.rk))
-                o.lay = semk::ALIAS;
-            else
-                all = false;
-        }
+        for (OrderChoice& o : p.orders)
+            all = all && default_shape(p.dtype, nt, o.nq, p.rk, &o.epb, &o.lay);
         if (all) {
             p.nt = nt;
             return SEM_OK;

@@ -208,6 +208,32 @@ def curl_metric_geo(xyz: np.ndarray, N: int) -> np.ndarray:
     return geo
 
 
+def box_neighbours(n_side, elements: Optional[np.ndarray] = None) -> np.ndarray:
+    """Face neighbours of the structured box of ``nx x ny x nz`` elements
+    ``e = ex + nx (ey + ny ez)``, periodic in every direction: ``nbr[e][f]``
+    for the faces f = r-, r+, s-, s+, t-, t+ (reference direction d = f // 2,
+    side f % 2), an int32 ``[Ne, 6]`` array indexing ``elements``.  A
+    neighbour outside the ``elements`` subset is ``-1`` (a boundary face).
+    Neighbouring elements of the box share the face with aligned node
+    numbering: node (0, j, k) of an element meets node (N, j, k) of the one
+    across its r = -1 face."""
+    nx, ny, nz = (n_side,) * 3 if np.isscalar(n_side) else tuple(n_side)
+    if elements is None:
+        elements = np.arange(nx * ny * nz)
+    elements = np.asarray(elements, dtype=np.int64)
+    pos = np.full(nx * ny * nz, -1, dtype=np.int64)
+    pos[elements] = np.arange(elements.size)
+    ex = elements % nx
+    ey = (elements // nx) % ny
+    ez = elements // (nx * ny)
+    nbr = np.empty((elements.size, 6), dtype=np.int32)
+    for f, (dx, dy, dz) in enumerate(((-1, 0, 0), (1, 0, 0), (0, -1, 0), (0, 1, 0),
+                                      (0, 0, -1), (0, 0, 1))):
+        g = (ex + dx) % nx + nx * ((ey + dy) % ny + ny * ((ez + dz) % nz))
+        nbr[:, f] = pos[g]
+    return nbr
+
+
 @dataclasses.dataclass
 class Mesh:
     N: int
@@ -369,6 +395,7 @@ class Workload:
     xyz: np.ndarray
     lam: Optional[np.ndarray] = None    # cotangent (Ne, 5, Nq^3)
     dq: Optional[np.ndarray] = None     # FD direction (Ne, 5, Nq^3)
+    nbr: Optional[np.ndarray] = None    # face neighbours (Ne, 6) int32, box meshes only
 
     @property
     def Nq(self) -> int:
@@ -408,7 +435,9 @@ def warped_workload(N: int = 7, n_side: int = 32, n_elements: Optional[int] = No
     total = n_side ** 3
     n = total if n_elements is None else int(n_elements)
     mesh = warped_mesh(N, n_side, np.arange(n), metrics=metrics)
-    return _finish(f"warped_N{N}_Ne{n}", N, mesh, rng, with_adjoint)
+    w = _finish(f"warped_N{N}_Ne{n}", N, mesh, rng, with_adjoint)
+    w.nbr = box_neighbours(n_side, np.arange(n))
+    return w
 
 
 def mixed_order_workloads(orders=(3, 5, 7, 9), per_order: int = 5000, k: int = 3):

@@ -36,6 +36,7 @@ EXPORTS = (
     "sem_axpby", "sem_batch_plan", "sem_batch_execute",
     "sem_plan_describe", "sem_plan_destroy", "sem_rk3_graph_create", "sem_rk3_graph_launch",
     "sem_rk3_graph_describe", "sem_rk3_graph_destroy", "sem_set_max_workgroups",
+    "sem_surface_rhs",
 )
 
 
@@ -97,6 +98,7 @@ def lib() -> ctypes.CDLL:
         "sem_rk3_graph_describe": ([vp, ctypes.c_char_p, i32], i32),
         "sem_rk3_graph_destroy": ([vp], i32),
         "sem_set_max_workgroups": ([i64], i32),
+        "sem_surface_rhs": ([i32, i32, i32, vp, vp, vp, vp, P(sem_phys), vp, i32, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -280,6 +282,30 @@ def volume_rhs_adjoint(q, geo, D, lam, phys=None, out=None, accumulate=False,
         Ne, Nq, _code(dt), _dev(D, "D", dt), _dev(geo, "geo", dt, (Ne, 10, M)), _dev(q, "q", dt),
         ctypes.byref(ph), _dev(lam, "lam", dt, q.shape), _dev(out, "out", dt, q.shape),
         int(bool(accumulate)), _stream(stream)))
+    return out
+
+
+def surface_rhs(q, geo, nbr, theta_ref=None, phys=None, out=None, accumulate=False,
+                stream=None) -> torch.Tensor:
+    """Surface term s of ``dq/dt = v + s`` (``out = s``, or ``out += s`` with
+    ``accumulate``): ``nbr`` is an int32 ``[Ne, 6]`` tensor of the elements
+    across the faces r-, r+, s-, s+, t-, t+ (an index outside ``[0, Ne)`` is a
+    boundary face that adds nothing)."""
+    if q.dim() != 3 or q.shape[1] != 5:
+        raise ValueError(f"q must be [Ne, 5, Nq^3], got {tuple(q.shape)}")
+    Ne, M = q.shape[0], q.shape[2]
+    Nq = round(M ** (1.0 / 3.0))
+    if Nq ** 3 != M:
+        raise ValueError(f"q's node count {M} is not a cube")
+    dt = q.dtype
+    if out is None:
+        out = torch.empty_like(q)
+    ph = _phys(phys)
+    _check(lib().sem_surface_rhs(
+        Ne, Nq, _code(dt), _dev(nbr, "nbr", torch.int32, (Ne, 6)),
+        _dev(geo, "geo", dt, (Ne, 10, M)), _dev(q, "q", dt),
+        _dev(theta_ref, "theta_ref", torch.float64, (Ne, M)), ctypes.byref(ph),
+        _dev(out, "out", dt, q.shape), int(bool(accumulate)), _stream(stream)))
     return out
 
 

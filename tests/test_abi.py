@@ -367,3 +367,27 @@ def test_max_workgroups_setter(L, sv):
     assert L.sem_set_max_workgroups(-1) == sv.SEM_ERR_INVALID_ARG
     assert L.sem_set_max_workgroups(7) == sv.SEM_OK
     assert L.sem_set_max_workgroups(0) == sv.SEM_OK
+
+
+def test_surface_validation(L, sv):
+    ph = sv.sem_phys(1e5, 1.4, 287.0, 9.81)
+    Ne, Nq = 4, 5
+    M = Nq ** 3
+
+    def surf(Ne=Ne, Nq=Nq, dt=0, nbr=B, geo=2 * B, q=3 * B, tr=None, rhs=4 * B, phys=True):
+        return L.sem_surface_rhs(Ne, Nq, dt, nbr, geo, q, tr, ctypes.byref(ph) if phys else None,
+                                 rhs, 0, None)
+    assert surf(Ne=0) == sv.SEM_ERR_INVALID_ARG
+    assert surf(Nq=11) == sv.SEM_ERR_UNSUPPORTED
+    assert surf(Nq=1) == sv.SEM_ERR_UNSUPPORTED
+    assert surf(dt=4) == sv.SEM_ERR_INVALID_ARG
+    assert surf(nbr=None) == sv.SEM_ERR_INVALID_ARG
+    assert surf(nbr=B + 2) == sv.SEM_ERR_INVALID_ARG          # int32 table misaligned
+    assert surf(q=3 * B + 4) == sv.SEM_ERR_INVALID_ARG
+    assert surf(tr=5 * B + 4) == sv.SEM_ERR_INVALID_ARG
+    assert surf(phys=False) == sv.SEM_ERR_INVALID_ARG
+    assert surf(rhs=3 * B + 8) == sv.SEM_ERR_INVALID_ARG       # overlaps q
+    assert b"overlaps q" in L.sem_last_error()
+    assert surf(rhs=B + 16) == sv.SEM_ERR_INVALID_ARG          # overlaps the neighbour table
+    assert b"overlaps nbr" in L.sem_last_error()
+    assert surf(tr=5 * B, rhs=5 * B + Ne * M * 8 - 8) == sv.SEM_ERR_INVALID_ARG

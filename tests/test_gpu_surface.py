@@ -1,0 +1,144 @@
+"""GPU parity of the surface term (the s of dq/dt = v + s: strong-form
+discontinuous Galerkin face term with a local Lax-Friedrichs flux) through the
+C-ABI, against the CPU oracle element by element.
+
+Gates as for the volume term: FP64 <= 1e-12, FP32 <= 2e-5 (oracle on the
+FP32-rounded inputs, upcast exactly, with the shared FP64 Theta_ref), max
+relative error per field normalised by max|oracle| of that field.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1604_08501_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 2e-5
+
+
+@pytest.fixture(scope="module")
+def sv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1604_08501_amd as m
+    m.lib()
+    return m
+
+
+def dev(a):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def err(out, ref):
+    return I.rel_err_per_field(out, ref)
+
+
+def run(sv, w, nbr=None, with_ref=True, out=None, accumulate=False, fp32=False):
+    src = I.to_fp32(w) if fp32 else w
+    return sv.surface_rhs(dev(src.q), dev(src.geo), dev(w.nbr if nbr is None else nbr),
+                          dev(w.theta_ref) if with_ref else None, w.phys.as_tuple(), out=out,
+                          accumulate=accumulate)
+
+
+def oracle_s(oracle_mod, w, nbr=None, with_ref=True, fp32=False):
+    src = I.upcast(I.to_fp32(w)) if fp32 else w
+    return oracle_mod.surface_rhs(src.geo, src.q, w.nbr if nbr is None else nbr,
+                                  w.theta_ref if with_ref else None, w.phys.as_tuple())
+
+
+@pytest.mark.parametrize("Nq", [2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16])
+def test_surface_vs_oracle(sv, oracle_mod, Nq):
+    """Every order on a periodic warped box (3^3 elements, 2^3 at Nq >= 12):
+    FP64 and FP32, with and without the reference state, overwrite and
+    accumulate."""
+    n_side = 3 if Nq <= 10 else 2
+    w = I.warped_workload(N=Nq - 1, n_side=n_side, k=300 + Nq)
+    for with_ref in (True, False):
+        ref = oracle_s(oracle_mod, w, with_ref=with_ref)
+        e = err(host(run(sv, w, with_ref=with_ref)), ref)
+        assert e.max() <= TOL64, (Nq, with_ref, e)
+        base = np.random.default_rng(Nq).standard_normal(w.q.shape)
+        out = dev(base.copy())
+        run(sv, w, with_ref=with_ref, out=out, accumulate=True)
+        assert err(host(out), base + ref).max() <= TOL64, (Nq, with_ref)
+        ref32 = oracle_s(oracle_mod, w, with_ref=with_ref, fp32=True)
+        e32 = err(host(run(sv, w, with_ref=with_ref, fp32=True)), ref32)
+        assert e32.max() <= TOL32, (Nq, with_ref, e32)
+        b32 = base.astype(np.float32)
+        out32 = dev(b32.copy())
+        run(sv, w, with_ref=with_ref, out=out32, accumulate=True, fp32=True)
+        assert err(host(out32), b32.astype(np.float64) + ref32).max() <= TOL32, (Nq, with_ref)
+
+
+def test_surface_boundary_faces_and_out_of_range_neighbours(sv, oracle_mod):
+    """A mesh cut out of the box (neighbours outside it are -1) with some
+    indices set beyond Ne or below -1: every such face is a boundary face and
+    adds nothing, exactly as in the oracle; the kernel reads nothing through
+    them."""
+    w = I.warped_workload(N=4, n_side=4, n_elements=21, k=320)
+    nbr = w.nbr.copy()
+    nbr[3, 1] = w.Ne + 5
+    nbr[7, 4] = 2 ** 31 - 1
+    nbr[11, 2] = -7
+    assert (nbr < 0).any()
+    ref = oracle_s(oracle_mod, w, nbr=nbr)
+    assert err(host(run(sv, w, nbr=nbr)), ref).max() <= TOL64
+    ref32 = oracle_s(oracle_mod, w, nbr=nbr, fp32=True)
+    assert err(host(run(sv, w, nbr=nbr, fp32=True)), ref32).max() <= TOL32
+    none = np.full_like(w.nbr, -1)
+    assert np.all(host(run(sv, w, nbr=none)) == 0.0)
+
+
+def test_single_element_periodic_onto_itself(sv, oracle_mod):
+    """One element whose six neighbours are itself (a 1^3 periodic box)."""
+    w = I.warped_workload(N=5, n_side=1, k=321)
+    assert np.all(w.nbr == 0)
+    assert err(host(run(sv, w)), oracle_s(oracle_mod, w)).max() <= TOL64
+
+
+def test_volume_plus_surface_is_conservative(sv, oracle_mod):
+    """sem_volume_rhs then sem_surface_rhs with accumulate gives v + s; on the
+    periodic box its GLL quadrature of J (v + s) vanishes (no source), as the
+    oracle's does."""
+    N = 4
+    w = I.warped_workload(N=N, n_side=4, k=322)
+    phys = (I.P0, I.GAMMA, I.R_GAS, 0.0)
+    q, geo, D, rr, tr = dev(w.q), dev(w.geo), dev(w.D), dev(w.rho_ref), dev(w.theta_ref)
+    out = sv.volume_rhs(q, geo, D, rr, tr, phys)
+    sv.surface_rhs(q, geo, dev(w.nbr), tr, phys, out=out, accumulate=True)
+    got = host(out)
+    ref = oracle_mod.volume_rhs(w.D, w.geo, w.q, w.rho_ref, w.theta_ref, phys) + \
+        oracle_mod.surface_rhs(w.geo, w.q, w.nbr, w.theta_ref, phys)
+    assert err(got, ref).max() <= TOL64
+    wq = I.gll_weights(N)
+    Nq = N + 1
+    m = np.arange(Nq ** 3)
+    W = (wq[m % Nq] * wq[(m // Nq) % Nq] * wq[m // (Nq * Nq)])[None, :] / w.geo[:, 9]
+    tot = np.einsum("em,ebm->b", W, got)
+    scale = np.einsum("em,ebm->b", W, np.abs(got))
+    assert np.all(np.abs(tot) <= 1e-13 * scale), tot / scale
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return I.warped_workload()          # N = 7, 32768 elements, periodic 32^3 box
+
+
+@pytest.mark.slow
+def test_surface_full_n7_32768(sv, oracle_mod, c2):
+    """The surface term at N = 7 on the whole periodic warped 32^3 box, FP64
+    and FP32, in the launch the benchmark times."""
+    ref = oracle_s(oracle_mod, c2)
+    e = err(host(run(sv, c2)), ref)
+    print("surface N=7 32768 fp64 err", e)
+    assert e.max() <= TOL64
+    ref32 = oracle_s(oracle_mod, c2, fp32=True)
+    e32 = err(host(run(sv, c2, fp32=True)), ref32)
+    print("surface N=7 32768 fp32 err", e32)
+    assert e32.max() <= TOL32

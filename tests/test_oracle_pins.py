@@ -488,3 +488,169 @@ def test_free_stream_on_curved_elements_with_curl_metrics(oracle_mod, N):
     va = oracle_mod.volume_rhs(D, I.warped_mesh(N, 32, els).geo, q, phys=phys)
     assert np.abs(vc).max() < 1e-9
     assert np.abs(va).max() > 100 * np.abs(vc).max()
+
+
+# ---------------------------------------------------------------------------
+# Surface term (the s of dq/dt = v + s): strong-form discontinuous Galerkin
+# face term with a local Lax-Friedrichs flux
+# ---------------------------------------------------------------------------
+NO_GRAV = (I.P0, I.GAMMA, I.R_GAS, 0.0)
+
+
+def _quad_weights(N):
+    w = I.gll_weights(N)
+    Nq = N + 1
+    m = np.arange(Nq ** 3)
+    return w[m % Nq] * w[(m // Nq) % Nq] * w[m // (Nq * Nq)]
+
+
+@pytest.mark.parametrize("N,metrics", [(2, "analytic"), (3, "analytic"), (5, "analytic"),
+                                       (4, "curl")])
+def test_surface_discrete_conservation(oracle_mod, N, metrics):
+    """On the periodic warped box, the GLL quadrature of J (v + s) over the
+    whole mesh vanishes for every field (no source): the summation-by-parts
+    property of D turns each element's volume term into its face fluxes, the
+    surface term replaces them by the numerical flux, and the two elements of
+    a face see opposite numerical fluxes.  The volume term alone does not
+    vanish (the random state jumps across faces)."""
+    w = I.warped_workload(N=N, n_side=4, k=200 + N, metrics=metrics)
+    v = oracle_mod.volume_rhs(w.D, w.geo, w.q, w.rho_ref, w.theta_ref, NO_GRAV)
+    s = oracle_mod.surface_rhs(w.geo, w.q, w.nbr, w.theta_ref, NO_GRAV)
+    WJ = _quad_weights(N)[None, :] / w.geo[:, 9]
+    tot = np.einsum("em,ebm->b", WJ, v + s)
+    scale = np.einsum("em,ebm->b", WJ, np.abs(v) + np.abs(s))
+    assert np.all(np.abs(tot) <= 1e-13 * scale), tot / scale
+    vol_only = np.abs(np.einsum("em,ebm->b", WJ, v)) / scale
+    assert np.all(vol_only > 1e-6), vol_only
+    # without a reference state (full pressure in every flux) as well
+    v0 = oracle_mod.volume_rhs(w.D, w.geo, w.q, None, None, NO_GRAV)
+    s0 = oracle_mod.surface_rhs(w.geo, w.q, w.nbr, None, NO_GRAV)
+    tot0 = np.einsum("em,ebm->b", WJ, v0 + s0)
+    scale0 = np.einsum("em,ebm->b", WJ, np.abs(v0) + np.abs(s0))
+    assert np.all(np.abs(tot0) <= 1e-13 * scale0), tot0 / scale0
+
+
+def test_surface_reference_cancels_where_it_is_continuous(oracle_mod):
+    """Away from the z-periodic faces (where the stratified reference jumps)
+    the reference pressure cancels between the numerical flux and the inner
+    flux: s with and without the reference agree to round-off there."""
+    w = I.warped_workload(N=3, n_side=4, k=205)
+    s1 = oracle_mod.surface_rhs(w.geo, w.q, w.nbr, w.theta_ref, w.phys.as_tuple())
+    s0 = oracle_mod.surface_rhs(w.geo, w.q, w.nbr, None, w.phys.as_tuple())
+    ez = np.arange(w.Ne) // 16
+    mid = (ez >= 1) & (ez <= 2)
+    assert np.abs(s1[mid] - s0[mid]).max() <= 1e-9 * np.abs(s0[mid]).max()
+    assert np.abs(s1[~mid] - s0[~mid]).max() > 1e-3 * np.abs(s0).max()
+
+
+@pytest.mark.parametrize("N", [2, 4])
+def test_surface_zero_for_a_continuous_state(oracle_mod, N):
+    """A state sampled from smooth periodic functions of the position has no
+    jump across any face: s is exactly zero on the elements away from the
+    periodic boundary (coincident nodes have bit-identical coordinates) and
+    at round-off level elsewhere, against its size for a random state."""
+    w = I.warped_workload(N=N, n_side=4, k=210 + N)
+    x, y, z = (w.xyz[:, a] / I.LENGTH for a in range(3))
+    tp = 2 * np.pi
+    rho = 1.0 + 0.05 * np.sin(tp * x) * np.cos(tp * y)
+    q = np.stack([rho, rho * 10 * np.sin(tp * z), rho * 5 * np.cos(tp * x),
+                  rho * 3 * np.sin(tp * (y + z)), rho * (300 + np.cos(tp * (x - z)))], axis=1)
+    s = oracle_mod.surface_rhs(w.geo, q, w.nbr, None, w.phys.as_tuple())
+    s_rand = oracle_mod.surface_rhs(w.geo, w.q, w.nbr, None, w.phys.as_tuple())
+    e = np.arange(w.Ne)
+    inner = (e % 4 >= 1) & (e % 4 <= 2) & ((e // 4) % 4 >= 1) & ((e // 4) % 4 <= 2) & \
+            (e // 16 >= 1) & (e // 16 <= 2)
+    assert inner.sum() == 8 and np.all(s[inner] == 0.0)
+    assert np.abs(s).max() <= 1e-12 * np.abs(s_rand).max()
+
+
+def _two_cubes(h=10.0, N=3):
+    """Two axis-aligned cubes of edge 2h side by side along x: element 0's
+    r = +1 face is element 1's r = -1 face; every other face is a boundary."""
+    Nq = N + 1
+    M = Nq ** 3
+    geo = np.zeros((2, 10, M))
+    for d in range(3):
+        geo[:, 3 * d + d] = h * h          # cofactor of h I
+    geo[:, 9] = 1.0 / h ** 3
+    nbr = np.array([[-1, 1, -1, -1, -1, -1], [0, -1, -1, -1, -1, -1]], dtype=np.int32)
+    return geo, nbr, Nq, M
+
+
+def _state(rho, u, theta, M):
+    return np.array([rho, rho * u, 0.0, 0.0, rho * theta])[:, None] * np.ones(M)
+
+
+def test_surface_density_jump_closed_form(oracle_mod):
+    """A density jump at rest with equal Theta (equal pressure) across one
+    face: the central flux difference vanishes and only the dissipation
+    remains, s_rho = +-lambda (rho+ - rho-) / (2 h w_N) at the face nodes
+    (lambda = the larger sound speed, the one of the lighter side), zero
+    everywhere else and in every other field."""
+    h, N = 10.0, 3
+    geo, nbr, Nq, M = _two_cubes(h, N)
+    q = np.stack([_state(1.0, 0.0, 300.0, M), _state(1.2, 0.0, 300.0 / 1.2, M)])
+    # Theta = rho theta equal on both sides: give both the same Theta
+    q[1, 4] = q[0, 4]
+    s = oracle_mod.surface_rhs(geo, q, nbr, None, NO_GRAV)
+    p = I.P0 * (I.R_GAS * 300.0 / I.P0) ** I.GAMMA
+    lam = np.sqrt(I.GAMMA * p / 1.0)
+    wN = 2.0 / (N * (N + 1))
+    m = np.arange(M)
+    face0 = m % Nq == N          # element 0, r = +1
+    face1 = m % Nq == 0          # element 1, r = -1
+    expect = np.zeros_like(s)
+    expect[0, 0, face0] = lam * 0.2 / (2 * h * wN)
+    expect[1, 0, face1] = -lam * 0.2 / (2 * h * wN)
+    np.testing.assert_allclose(s, expect, rtol=1e-14, atol=1e-12 * np.abs(expect).max())
+
+
+def test_surface_normal_velocity_jump_closed_form(oracle_mod):
+    """Equal density and Theta, the neighbour moving away at u = 10 m/s
+    normal to the face: at element 0's face nodes the central flux difference
+    carries (U, U^2/rho, U Theta/rho) of the neighbour, the dissipation acts on
+    the momentum jump with lambda = |u| + c, so s_rho = -5/(h w_N),
+    s_U1 = 5 c/(h w_N), s_Theta = -1500/(h w_N); at the neighbour's face
+    nodes the signs of the normal flip: s_rho = -5/(h w_N),
+    s_U1 = -(50 + 5 (10 + c) - ... ) as below."""
+    h, N = 10.0, 4
+    geo, nbr, Nq, M = _two_cubes(h, N)
+    q = np.stack([_state(1.0, 0.0, 300.0, M), _state(1.0, 10.0, 300.0, M)])
+    s = oracle_mod.surface_rhs(geo, q, nbr, None, NO_GRAV)
+    p = I.P0 * (I.R_GAS * 300.0 / I.P0) ** I.GAMMA
+    c = np.sqrt(I.GAMMA * p)
+    wN = 2.0 / (N * (N + 1))
+    k = 1.0 / (h * wN)
+    m = np.arange(M)
+    f0, f1 = m % Nq == N, m % Nq == 0
+    # element 0 (outward normal +x h^2): flux jump F+ - F- = h^2 (10, 100, 0, 0, 3000),
+    # jump q+ - q- = (0, 10, 0, 0, 0), lambda = 10 + c
+    np.testing.assert_allclose(s[0, 0, f0], -k * 5.0, rtol=1e-14)
+    np.testing.assert_allclose(s[0, 1, f0], -k * (50.0 - 5.0 * (10.0 + c)), rtol=1e-13)
+    np.testing.assert_allclose(s[0, 4, f0], -k * 1500.0, rtol=1e-14)
+    # element 1 (outward normal -x h^2): F+ - F- = -h^2 (0 - 10, 0 - 100, 0, 0, 0 - 3000),
+    # q+ - q- = (0, -10, 0, 0, 0)
+    np.testing.assert_allclose(s[1, 0, f1], -k * 5.0, rtol=1e-14)
+    np.testing.assert_allclose(s[1, 1, f1], -k * (50.0 + 5.0 * (10.0 + c)), rtol=1e-13)
+    np.testing.assert_allclose(s[1, 4, f1], -k * 1500.0, rtol=1e-14)
+    assert np.all(s[:, 2:4] == 0.0)
+    assert np.all(s[0][:, ~f0] == 0.0) and np.all(s[1][:, ~f1] == 0.0)
+
+
+def test_surface_is_local_to_the_face_neighbours(oracle_mod):
+    """s of an element depends only on it and its six face neighbours: the
+    same element inside a 7-element sub-mesh (neighbours renumbered, the
+    sub-mesh's outer faces boundaries) gets bit-identical values; with every
+    face a boundary s vanishes."""
+    w = I.warped_workload(N=3, n_side=4, k=220)
+    full = oracle_mod.surface_rhs(w.geo, w.q, w.nbr, w.theta_ref, w.phys.as_tuple())
+    e = 21
+    sub = np.concatenate([[e], w.nbr[e]]).astype(np.int64)
+    pos = {int(g): i for i, g in enumerate(sub)}
+    nbr = np.full((7, 6), -1, dtype=np.int32)
+    nbr[0] = np.arange(1, 7)
+    part = oracle_mod.surface_rhs(w.geo[sub], w.q[sub], nbr, w.theta_ref[sub], w.phys.as_tuple())
+    assert np.array_equal(part[0], full[e])
+    none = np.full_like(w.nbr, -1)
+    assert np.all(oracle_mod.surface_rhs(w.geo, w.q, none, w.theta_ref, w.phys.as_tuple()) == 0.0)
+    assert pos[int(w.nbr[e][0])] == 1
