@@ -332,10 +332,18 @@ def surface_bytes_per_element(Nq: int, esz: int) -> int:
     return (16 * esz + 8) * nb + 3 * esz * 6 * Nq * Nq + 24
 
 
+def rhs_bytes_per_element(Nq: int, tag: str) -> int:
+    """Algorithmic bytes of the whole rate v + s per element: the volume
+    term's inputs and outputs (the surface term's values are the same
+    arrays, read once) and the six neighbour indices."""
+    return BYTES_PER_NODE[tag] * Nq ** 3 + 24
+
+
 def bench_surface(sv, I, w, steps: int, warmup: int, stream):
     """Surface term (strong-form DG face term, local Lax-Friedrichs flux) at
     N=7 on the periodic warped 32^3 box, accumulated into rhs; and the whole
-    rate v + s (the volume launch, then the surface launch)."""
+    rate v + s, as the volume launch followed by the surface launch and as one
+    launch."""
     import torch
     Ne, Nq = w.Ne, w.Nq
     out = {"workload": "surface term, N=7, 32768 warped elements, periodic, rhs += s",
@@ -354,15 +362,26 @@ def bench_surface(sv, I, w, steps: int, warmup: int, stream):
             sv.volume_rhs(q, geo, D, rr, tr, ph, out=rhs)
             sv.surface_rhs(q, geo, nbr, tr, ph, out=rhs, accumulate=True)
         ms_full, _, _ = time_launches(full, steps, warmup, stream)
+        # the whole rate in one launch: every input read once, rhs written once
+        ms_one, med_one, _ = time_launches(
+            lambda: sv.rhs(q, geo, D, nbr, rr, tr, ph, out=rhs), steps, warmup, stream)
         esz = 8 if tag == "f64" else 4
         bpe = surface_bytes_per_element(Nq, esz)
         gbs = bpe * Ne / (ms * 1e-3) / 1e9
+        bpe_one = rhs_bytes_per_element(Nq, tag)
+        gbs_one = bpe_one * Ne / (ms_one * 1e-3) / 1e9
         out["bytes_per_element"][tag] = bpe
         out[tag] = {"ms": ms, "median_ms": med, "el_s": Ne / (ms * 1e-3), "GBs": gbs,
                     "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
                                  "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS},
                     "volume_plus_surface_ms": ms_full,
-                    "volume_plus_surface_el_s": Ne / (ms_full * 1e-3)}
+                    "volume_plus_surface_el_s": Ne / (ms_full * 1e-3),
+                    "one_launch": {"ms": ms_one, "median_ms": med_one, "el_s": Ne / (ms_one * 1e-3),
+                                   "bytes_per_element": bpe_one, "GBs": gbs_one,
+                                   "roofline": {"bound": "hbm", "achieved": gbs_one,
+                                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                                "frac": gbs_one / HBM_PEAK_GBS},
+                                   "speedup_vs_two_launches": ms_full / ms_one}}
         del q, geo, D, rr, tr, nbr, rhs
         torch.cuda.empty_cache()
     return out

@@ -275,6 +275,24 @@ sem_status sem_surface_rhs(int32_t Ne, int32_t Nq, sem_dtype dtype, const int32_
                            const void* geo, const void* q, const double* theta_ref,
                            const sem_phys* phys, void* rhs, int32_t accumulate, void* stream);
 
+/* The whole rate dq/dt = v(q) + s(q) of Sec. 2 in one kernel launch: the
+ * volume term of sem_volume_rhs and the surface term of sem_surface_rhs,
+ * evaluated together so that every input is read once and rhs is written
+ * once.  rhs = v + s (accumulate == 0) or rhs += v + s.  Arguments and
+ * layouts as for sem_volume_rhs, plus nbr [Ne][6] as for sem_surface_rhs
+ * (conforming aligned faces; a neighbour index outside [0, Ne) is a boundary
+ * face that adds nothing).  The result equals sem_volume_rhs followed by
+ * sem_surface_rhs with accumulate up to rounding (the face terms join the
+ * sum before the 1/J scaling).
+ * Nq: 2..10.
+ * No byte of rhs may lie inside an input (D, geo, q, rho_ref, theta_ref, nbr).
+ * Errors: as for sem_volume_rhs; NULL or misaligned nbr -> SEM_ERR_INVALID_ARG.
+ * Allocates nothing; enqueues one kernel launch. */
+sem_status sem_rhs(int32_t Ne, int32_t Nq, sem_dtype dtype, const void* D, const void* geo,
+                   const void* q, const void* rho_ref, const double* theta_ref,
+                   const int32_t* nbr, const sem_phys* phys, void* rhs, int32_t accumulate,
+                   void* stream);
+
 /* out[i] = a*x[i] + b*(y[i] + c*z[i]) for i < n (x may be NULL when a == 0):
  * the stage update of an explicit Runge-Kutta method for the method-of-lines
  * system dq/dt = v(q) + s(q) of Sec. 2 (with y the stage state, z its rate

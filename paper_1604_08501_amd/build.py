@@ -24,6 +24,7 @@ INCLUDE = os.path.join(os.path.dirname(PKG), "include")
 ARCH = "gfx950"
 SOURCES = [
     "ext_f64.hip", "ext_f32.hip", "ladder.hip", "surface_f64.hip", "surface_f32.hip",
+    "rhs_f64.hip", "rhs_f32.hip",
     "batch_f64.hip", "batch_f32.hip",
     "kernels_f64.hip", "kernels_f32.hip",
     "sem_api.cpp", "sem_plan.cpp",

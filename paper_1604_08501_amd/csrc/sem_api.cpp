@@ -528,3 +528,35 @@ extern "C" sem_status sem_axpby(int64_t n, sem_dtype dtype, double a, const void
 // ===========================================================================
 // Batch plans
 // ===========================================================================
+
+extern "C" sem_status sem_rhs(int32_t Ne, int32_t Nq, sem_dtype dtype, const void* D,
+                              const void* geo, const void* q, const void* rho_ref,
+                              const double* theta_ref, const int32_t* nbr, const sem_phys* phys,
+                              void* rhs, int32_t accumulate, void* stream)
+{
+    SEM_TRY(check_volume_args(Ne, Nq, dtype, D, geo, q, rho_ref, theta_ref, phys, rhs));
+    const bool ok = dtype == SEM_F64 ? semh::rhs_supported<double>(Nq)
+                                     : semh::rhs_supported<float>(Nq);
+    if (!ok)
+        return fail(SEM_ERR_UNSUPPORTED, "Nq = %d is not compiled for the whole rate (Nq 2..10)",
+                    Nq);
+    SEM_TRY(check_ptr(nbr, 4, "nbr"));
+    {
+        const ByteRange in[] = {{"nbr", nbr, (size_t)Ne * 6 * 4}};
+        SEM_TRY(check_output_overlap("rhs", rhs, (size_t)Ne * 5 * Nq * Nq * Nq * elem_size(dtype),
+                                     in, 1));
+    }
+    const semk::Phys ph = to_phys(phys);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const hipError_t err =
+        dtype == SEM_F64
+            ? semh::launch_volume_surface<double>(
+                  Nq, block_ptrs<double>(Ne, D, geo, q, rho_ref, theta_ref, rhs), nbr, ph,
+                  accumulate, s)
+            : semh::launch_volume_surface<float>(
+                  Nq, block_ptrs<float>(Ne, D, geo, q, rho_ref, theta_ref, rhs), nbr, ph,
+                  accumulate, s);
+    if (err != hipSuccess)
+        return hip_fail(err, "volume + surface kernel launch");
+    return SEM_OK;
+}

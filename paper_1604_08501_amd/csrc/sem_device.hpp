@@ -111,6 +111,16 @@ struct Pressure<double> {
             x -= xgamma(s * thr, ph);
         return ph.p0 * x;
     }
+    // the flux pressure of eval() and the full pressure p (for the sound
+    // speed of the surface term's dissipation)
+    static __device__ __forceinline__ void eval_full(double Th, bool has_ref, double thr,
+                                                     const Phys& ph, double& pflux, double& pfull)
+    {
+        const double s = ph.r_over_p0;
+        const double x = xgamma(s * Th, ph);
+        pfull = ph.p0 * x;
+        pflux = has_ref ? ph.p0 * (x - xgamma(s * thr, ph)) : pfull;
+    }
     // dp/dTheta = gamma p / Theta (full pressure, for the adjoint)
     static __device__ __forceinline__ double dp_dtheta(double Th, const Phys& ph)
     {
@@ -146,6 +156,21 @@ struct Pressure<float> {
     {
         const float p0 = (float)ph.p0, g = (float)ph.gamma, s = (float)ph.r_over_p0;
         return g * (p0 * xgamma(s * Th, g)) / Th;
+    }
+    // eval() and the full pressure p_ref + p' (or p)
+    static __device__ __forceinline__ void eval_full(float Th, bool has_ref, double thr,
+                                                     const Phys& ph, float& pflux, float& pfull)
+    {
+        const float p0 = (float)ph.p0, g = (float)ph.gamma, s = (float)ph.r_over_p0;
+        if (has_ref) {
+            const float dth = (float)((double)Th - thr);
+            const float trf = (float)thr;
+            const float pref = p0 * xgamma(s * trf, g);
+            pflux = pref * expm1f(g * log1pf(dth / trf));
+            pfull = pref + pflux;
+        } else {
+            pfull = pflux = p0 * xgamma(s * Th, g);
+        }
     }
 };
 
@@ -315,6 +340,7 @@ __device__ __forceinline__ void store_node(const BlockPtrs<T>& B, const RkStage&
 template <typename T, int NF>
 struct NodeState {
     T rho, U1, U2, U3, Th, rinv, pp, jinv, src;
+    T pfull;   // full pressure (FULLP loads only)
     T g[9];
     T Q[NF > 5 ? NF - 5 : 1];
 };
@@ -324,8 +350,11 @@ struct NodeState {
 // reads through the cache (for tiles whose consecutive accesses share cache
 // lines).  SRC = false leaves the gravity source out (src = 0, rho_ref not
 // read), for a pass that adds one direction's term to a finished rhs.
+// FULLP = true also keeps the full pressure (for the surface term) and reads
+// the state and Theta_ref through the cache: the face neighbours of the
+// element read its face values again.
 template <typename T, int M, int NF, int DIRS, bool GEOE = false, bool STREAM = true,
-          bool SRC = true>
+          bool SRC = true, bool FULLP = false>
 __device__ __forceinline__ void load_node(const BlockPtrs<T>& B, const Phys& ph, int64_t e, int m,
                                           NodeState<T, NF>& st)
 {
@@ -335,16 +364,17 @@ __device__ __forceinline__ void load_node(const BlockPtrs<T>& B, const Phys& ph,
     // per-element metric records are shared by every node of the element and
     // stay cached; everything else streams
     auto ld = [](const auto* p) { return STREAM ? ld_stream(p) : *p; };
+    auto ldq = [](const auto* p) { return (STREAM && !FULLP) ? ld_stream(p) : *p; };
     auto geo_at = [&](int s) { return GEOE ? ge[s * GS] : ld(ge + s * GS); };
-    const T rho = ld(qe);
+    const T rho = ldq(qe);
     st.rho = rho;
-    st.U1 = ld(qe + M);
-    st.U2 = ld(qe + 2 * M);
-    st.U3 = ld(qe + 3 * M);
-    st.Th = ld(qe + 4 * M);
+    st.U1 = ldq(qe + M);
+    st.U2 = ldq(qe + 2 * M);
+    st.U3 = ldq(qe + 3 * M);
+    st.Th = ldq(qe + 4 * M);
 #pragma unroll
     for (int b = 5; b < NF; ++b)
-        st.Q[b - 5] = ld(qe + b * M);
+        st.Q[b - 5] = ldq(qe + b * M);
 #pragma unroll
     for (int s = 0; s < 9; ++s)
         st.g[s] = ((DIRS >> (s / 3)) & 1) ? geo_at(s) : (T)0;
@@ -355,10 +385,13 @@ __device__ __forceinline__ void load_node(const BlockPtrs<T>& B, const Phys& ph,
     if (has_ref) {
         if constexpr (SRC)
             rr = ld(B.rho_ref + e * M + m);
-        thr = ld(B.theta_ref + e * M + m);
+        thr = ldq(B.theta_ref + e * M + m);
     }
     st.src = SRC ? -(T)ph.grav * (rho - rr) : (T)0;
-    st.pp = Pressure<T>::eval(st.Th, has_ref, thr, ph);
+    if constexpr (FULLP)
+        Pressure<T>::eval_full(st.Th, has_ref, thr, ph, st.pp, st.pfull);
+    else
+        st.pp = Pressure<T>::eval(st.Th, has_ref, thr, ph);
     st.rinv = (T)1 / rho;
 }
 
@@ -479,6 +512,162 @@ __device__ __forceinline__ void contract_r_lanes(const T* __restrict__ sD, const
 }
 
 // ---------------------------------------------------------------------------
+// Surface term of dq/dt = v + s fused into the forward tile's epilogue (the
+// strong-form discontinuous Galerkin face term with a local Lax-Friedrichs
+// flux; see the surface kernel for the formula).  Faces f = 2 d + side of an
+// element; a face node is named by its indices (a2, b2) along the face's two
+// tangential directions (for d = r: s, t; for s: r, t; for t: r, s), and
+// meets the node with the same tangential indices at the other end of
+// direction d in the element across the face.
+// ---------------------------------------------------------------------------
+
+// Workgroup index whose elements this workgroup handles: hardware workgroup
+// b runs on accelerator complex die (XCD) b mod 8 of MI355X; the first
+// 8 floor(G/8) workgroups are re-dealt so that XCD x handles logical
+// workgroups [x G8/8, (x+1) G8/8) in order, which keeps an element and its
+// neighbours along r and s on one XCD's L2 at about the same time.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int64_t xcd_contiguous_block(int64_t b, int64_t G)
+{
+    const int64_t G8 = (G / kXcds) * kXcds;
+    if (b >= G8)
+        return b;
+    const int64_t per = G8 / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+
+// Values staged per neighbour face node: the state (5), the flux pressure
+// and the sound speed sqrt(gamma p / rho) of the full pressure.
+constexpr int kFaceVals = 7;
+
+template <int NQ>
+constexpr int face_lds_values_per_element()
+{
+    return 6 * kFaceVals * NQ * NQ;
+}
+
+// Node of face (d, side) with tangential indices (a2, b2).
+template <int NQ>
+__device__ __forceinline__ int face_node(int d, int side, int a2, int b2)
+{
+    const int sd = d == 0 ? 1 : (d == 1 ? NQ : NQ * NQ);
+    const int sa = d == 0 ? NQ : 1;
+    const int sb = d == 2 ? NQ : NQ * NQ;
+    return (side ? NQ - 1 : 0) * sd + a2 * sa + b2 * sb;
+}
+
+// The tile's neighbour face values into LDS, sF[es][f][v][a2 + NQ b2]: for
+// face f of tile element es, the state of the element across f at its node
+// facing ours, its flux pressure and its sound speed.  Faces whose neighbour
+// index lies outside [0, Ne) are boundary faces: nothing is read.
+template <typename T, int NQ, int EPB, int NT>
+__device__ __forceinline__ void stage_neighbour_faces(const BlockPtrs<T>& B,
+                                                      const int32_t* __restrict__ nbr,
+                                                      const Phys& ph, int64_t e0, int ne,
+                                                      T* __restrict__ sFace)
+{
+    constexpr int NQ2 = NQ * NQ;
+    constexpr int M = NQ2 * NQ;
+    constexpr int PER = 6 * NQ2;
+    const bool has_ref = B.theta_ref != nullptr;
+    const T gam = (T)ph.gamma;
+#pragma unroll 1
+    for (int x = threadIdx.x; x < EPB * PER; x += NT) {
+        const int es = x / PER;
+        const int r = x - es * PER;
+        const int f = r / NQ2;
+        const int a = r - f * NQ2;
+        if (es >= ne)
+            continue;
+        const int64_t en = nbr[(e0 + es) * 6 + f];
+        if (en < 0 || en >= B.Ne)
+            continue;
+        const int d = f >> 1, side = f & 1;
+        const int mp = face_node<NQ>(d, 1 - side, a % NQ, a / NQ);
+        const T* __restrict__ qn = B.q + en * (5 * M) + mp;
+        T v[kFaceVals];
+#pragma unroll
+        for (int b = 0; b < 5; ++b)
+            v[b] = qn[b * M];
+        const double thr = has_ref ? B.theta_ref[en * M + mp] : 0.0;
+        T pfull;
+        Pressure<T>::eval_full(v[4], has_ref, thr, ph, v[5], pfull);
+        v[6] = sqrt(gam * pfull / v[0]);
+        T* __restrict__ o = sFace + es * (kFaceVals * PER) + f * (kFaceVals * NQ2) + a;
+#pragma unroll
+        for (int b = 0; b < kFaceVals; ++b)
+            o[b * NQ2] = v[b];
+    }
+}
+
+// acc[b] += (1/w_N) sum over the node's faces of (F*_b - Fn_b(q-)), so that
+// the epilogue's -(1/J) acc + source is v + s.  st: the node's own state and
+// full pressure; (i, j, k): its indices; nb: the element's six neighbour
+// indices; sFe: the element's staged neighbour faces.
+template <typename T, int NQ>
+__device__ __forceinline__ void add_face_terms(const NodeState<T, 5>& st, int i, int j, int k,
+                                               const int32_t* __restrict__ nb, int64_t Ne,
+                                               const T* __restrict__ sFe, T gam, T lift,
+                                               T (&acc)[5])
+{
+    constexpr int NQ2 = NQ * NQ;
+    constexpr int N = NQ - 1;
+    const int ijk[3] = {i, j, k};
+    if (!(i == 0 || i == N || j == 0 || j == N || k == 0 || k == N))
+        return;
+    const T cm = sqrt(gam * st.pfull * st.rinv);
+    const T qm[5] = {st.rho, st.U1, st.U2, st.U3, st.Th};
+    T sacc[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int id = ijk[d];
+        if (id != 0 && id != N)
+            continue;
+        const int side = id == N ? 1 : 0;
+        const int64_t en = nb[2 * d + side];
+        if (en < 0 || en >= Ne)
+            continue;   // boundary face: exterior state = interior state
+        const int a = d == 0 ? j + NQ * k : (d == 1 ? i + NQ * k : i + NQ * j);
+        const T* __restrict__ v = sFe + (2 * d + side) * (kFaceVals * NQ2) + a;
+        T qp[5];
+#pragma unroll
+        for (int b = 0; b < 5; ++b)
+            qp[b] = v[b * NQ2];
+        const T pp_flux = v[5 * NQ2], cp = v[6 * NQ2];
+        const T sg = side ? (T)1 : (T)-1;
+        const T n0 = sg * st.g[3 * d], n1 = sg * st.g[3 * d + 1], n2 = sg * st.g[3 * d + 2];
+        const T nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+        const T rinv_p = (T)1 / qp[0];
+        const T NUm = n0 * qm[1] + n1 * qm[2] + n2 * qm[3];
+        const T NUp = n0 * qp[1] + n1 * qp[2] + n2 * qp[3];
+        const T vm = NUm * st.rinv, vp = NUp * rinv_p;   // N . u on each side
+        const T lam_m = fabs(vm) / nn + cm;
+        const T lam_p = fabs(vp) / nn + cp;
+        const T diss = (T)0.5 * (lam_m > lam_p ? lam_m : lam_p) * nn;
+        const T dp = pp_flux - st.pp;
+        const T dF[5] = {NUp - NUm, qp[1] * vp - qm[1] * vm + n0 * dp,
+                         qp[2] * vp - qm[2] * vm + n1 * dp, qp[3] * vp - qm[3] * vm + n2 * dp,
+                         qp[4] * vp - qm[4] * vm};
+#pragma unroll
+        for (int b = 0; b < 5; ++b)
+            sacc[b] += (T)0.5 * dF[b] - diss * (qp[b] - qm[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < 5; ++b)
+        acc[b] += lift * sacc[b];
+}
+
+// Inputs of the fused surface term: the neighbour table, 1/w_N, and the
+// LDS of the staged neighbour faces.
+template <typename T>
+struct SurfIn {
+    const int32_t* nbr;
+    T lift;
+    T* sFace;
+};
+
+// ---------------------------------------------------------------------------
 // Forward tile: EPB elements starting at e0, of which the first ne exist.
 // ---------------------------------------------------------------------------
 template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK, int NF, int DIRS, bool GEOE,
@@ -589,12 +778,18 @@ __device__ __forceinline__ void volume_tile_full(const BlockPtrs<T>& B, int64_t 
     }
 }
 
+// SURF: rhs = v + s, with the neighbour faces staged in sv.sFace during the
+// state loads and the face terms added in the epilogue (five fields, all
+// three directions).
 template <typename T, int NQ, int EPB, int NT, bool ACC, bool RK, int NF, int DIRS, bool GEOE,
-          int UNR = 2>
+          int UNR = 2, bool SURF = false>
 __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t e0, int ne,
                                                   const Phys& ph, const RkStage& rk,
-                                                  T* __restrict__ smem)
+                                                  T* __restrict__ smem,
+                                                  const SurfIn<T>& sv = SurfIn<T>{})
 {
+    static_assert(!SURF || (NF == 5 && DIRS == 7 && !GEOE), "the fused surface term is for the "
+                                                            "five-field r+s+t volume term");
     constexpr int NQ2 = Shape<NQ>::NQ2;
     constexpr int M = Shape<NQ>::M;
     constexpr int NODES = EPB * M;
@@ -625,10 +820,12 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
             acc[p][b] = (T)0;
         if (live[p]) {
             const int es = t / M;
-            load_node<T, M, NF, DIRS, GEOE>(B, ph, e0 + es, t - es * M, st[p]);
+            load_node<T, M, NF, DIRS, GEOE, true, true, SURF>(B, ph, e0 + es, t - es * M, st[p]);
             rn[p].load(B, rk, e0 + es, t - es * M, M, st[p]);
         }
     }
+    if constexpr (SURF)
+        stage_neighbour_faces<T, NQ, EPB, NT>(B, sv.nbr, ph, e0, ne, sv.sFace);
     if constexpr (RREG) {
 #pragma unroll
         for (int p = 0; p < NPT; ++p)
@@ -668,6 +865,12 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
         if (live[p]) {
             const int t = tid + p * NT;
             const int es = t / M;
+            if constexpr (SURF) {
+                const int m = t - es * M;
+                add_face_terms<T, NQ>(st[p], m % NQ, (m / NQ) % NQ, m / NQ2, sv.nbr + (e0 + es) * 6,
+                                      B.Ne, sv.sFace + es * face_lds_values_per_element<NQ>(),
+                                      (T)ph.gamma, sv.lift, acc[p]);
+            }
             store_node<T, M, NF, ACC, RK>(B, rk, e0 + es, t - es * M, acc[p], st[p].jinv,
                                           st[p].src, rn[p]);
         }

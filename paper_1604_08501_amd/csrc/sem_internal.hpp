@@ -77,6 +77,13 @@ template <typename T>
 hipError_t launch_surface(int nq, const semk::SurfPtrs<T>& B, const semk::Phys& ph, int accumulate,
                           hipStream_t s);
 
+// Volume + surface term in one launch (rhs_*.hip): Nq 2..10.
+template <typename T>
+bool rhs_supported(int nq);
+template <typename T>
+hipError_t launch_volume_surface(int nq, const semk::BlockPtrs<T>& B, const int32_t* nbr,
+                                 const semk::Phys& ph, int accumulate, hipStream_t s);
+
 // Workgroup cap of the strided k-slice and t-column launches set by
 // sem_set_max_workgroups (0 = none); one relaxed atomic load.
 int64_t max_workgroups_cap();

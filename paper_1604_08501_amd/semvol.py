@@ -36,7 +36,7 @@ EXPORTS = (
     "sem_axpby", "sem_batch_plan", "sem_batch_execute",
     "sem_plan_describe", "sem_plan_destroy", "sem_rk3_graph_create", "sem_rk3_graph_launch",
     "sem_rk3_graph_describe", "sem_rk3_graph_destroy", "sem_set_max_workgroups",
-    "sem_surface_rhs",
+    "sem_surface_rhs", "sem_rhs",
 )
 
 
@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
         "sem_rk3_graph_destroy": ([vp], i32),
         "sem_set_max_workgroups": ([i64], i32),
         "sem_surface_rhs": ([i32, i32, i32, vp, vp, vp, vp, P(sem_phys), vp, i32, vp], i32),
+        "sem_rhs": ([i32, i32, i32, vp, vp, vp, vp, vp, vp, P(sem_phys), vp, i32, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -306,6 +307,25 @@ def surface_rhs(q, geo, nbr, theta_ref=None, phys=None, out=None, accumulate=Fal
         _dev(geo, "geo", dt, (Ne, 10, M)), _dev(q, "q", dt),
         _dev(theta_ref, "theta_ref", torch.float64, (Ne, M)), ctypes.byref(ph),
         _dev(out, "out", dt, q.shape), int(bool(accumulate)), _stream(stream)))
+    return out
+
+
+def rhs(q, geo, D, nbr, rho_ref=None, theta_ref=None, phys=None, out=None, accumulate=False,
+        stream=None) -> torch.Tensor:
+    """The whole rate ``v(q) + s(q)`` (volume and surface term, Sec. 2) in one
+    launch: ``out = v + s`` or ``out += v + s``; ``nbr`` ``[Ne, 6]`` int32 as
+    for :func:`surface_rhs`."""
+    Ne, Nq = _shape(q, D)
+    M = Nq ** 3
+    dt = q.dtype
+    if out is None:
+        out = torch.empty_like(q)
+    ph = _phys(phys)
+    _check(lib().sem_rhs(Ne, Nq, _code(dt), _dev(D, "D", dt), _dev(geo, "geo", dt, (Ne, 10, M)),
+                         _dev(q, "q", dt), _dev(rho_ref, "rho_ref", dt, (Ne, M)),
+                         _dev(theta_ref, "theta_ref", torch.float64, (Ne, M)),
+                         _dev(nbr, "nbr", torch.int32, (Ne, 6)), ctypes.byref(ph),
+                         _dev(out, "out", dt, q.shape), int(bool(accumulate)), _stream(stream)))
     return out
 
 

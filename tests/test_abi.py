@@ -391,3 +391,28 @@ def test_surface_validation(L, sv):
     assert surf(rhs=B + 16) == sv.SEM_ERR_INVALID_ARG          # overlaps the neighbour table
     assert b"overlaps nbr" in L.sem_last_error()
     assert surf(tr=5 * B, rhs=5 * B + Ne * M * 8 - 8) == sv.SEM_ERR_INVALID_ARG
+
+
+def test_rhs_validation(L, sv):
+    """The one-launch v + s rejects what the volume term and the surface
+    term reject, before any HIP call."""
+    ph = sv.sem_phys(1e5, 1.4, 287.0, 9.81)
+    Ne, Nq = 4, 5
+    M = Nq ** 3
+
+    def rhs(Ne=Ne, Nq=Nq, dt=0, D=B, geo=2 * B, q=3 * B, rr=None, tr=None, nbr=5 * B, out=6 * B,
+            phys=True):
+        return L.sem_rhs(Ne, Nq, dt, D, geo, q, rr, tr, nbr, ctypes.byref(ph) if phys else None,
+                         out, 0, None)
+    assert rhs(Ne=0) == sv.SEM_ERR_INVALID_ARG
+    assert rhs(Nq=12) == sv.SEM_ERR_UNSUPPORTED
+    assert rhs(Nq=1) == sv.SEM_ERR_UNSUPPORTED
+    assert rhs(dt=4) == sv.SEM_ERR_INVALID_ARG
+    assert rhs(nbr=None) == sv.SEM_ERR_INVALID_ARG
+    assert rhs(nbr=5 * B + 2) == sv.SEM_ERR_INVALID_ARG          # int32 table misaligned
+    assert rhs(q=None) == sv.SEM_ERR_INVALID_ARG
+    assert rhs(rr=4 * B) == sv.SEM_ERR_INVALID_ARG               # reference pair incomplete
+    assert rhs(phys=False) == sv.SEM_ERR_INVALID_ARG
+    assert rhs(out=3 * B + 8) == sv.SEM_ERR_INVALID_ARG          # overlaps q
+    assert rhs(out=5 * B + 16) == sv.SEM_ERR_INVALID_ARG         # overlaps the neighbour table
+    assert b"overlaps nbr" in L.sem_last_error()

@@ -142,3 +142,97 @@ def test_surface_full_n7_32768(sv, oracle_mod, c2):
     e32 = err(host(run(sv, c2, fp32=True)), ref32)
     print("surface N=7 32768 fp32 err", e32)
     assert e32.max() <= TOL32
+
+
+# ---------------------------------------------------------------------------
+# The whole rate v + s in one launch (sem_rhs)
+# ---------------------------------------------------------------------------
+def run_rhs(sv, w, nbr=None, with_ref=True, out=None, accumulate=False, fp32=False):
+    src = I.to_fp32(w) if fp32 else w
+    return sv.rhs(dev(src.q), dev(src.geo), dev(src.D), dev(w.nbr if nbr is None else nbr),
+                  dev(src.rho_ref) if with_ref else None, dev(w.theta_ref) if with_ref else None,
+                  w.phys.as_tuple(), out=out, accumulate=accumulate)
+
+
+def oracle_vs(oracle_mod, w, nbr=None, with_ref=True, fp32=False):
+    src = I.upcast(I.to_fp32(w)) if fp32 else w
+    ph = w.phys.as_tuple()
+    rr, tr = (src.rho_ref, w.theta_ref) if with_ref else (None, None)
+    v = oracle_mod.volume_rhs(src.D, src.geo, src.q, rr, tr, ph)
+    return v + oracle_mod.surface_rhs(src.geo, src.q, w.nbr if nbr is None else nbr, tr, ph)
+
+
+@pytest.mark.parametrize("Nq", list(range(2, 11)))
+def test_rhs_vs_oracle(sv, oracle_mod, Nq):
+    """v + s in one launch against the oracle's volume term plus its surface
+    term, every order, on a periodic warped box (several tiles and a ragged
+    tail): FP64 and FP32, with and without the reference state, overwrite
+    and accumulate."""
+    w = I.warped_workload(N=Nq - 1, n_side=4 if Nq <= 4 else 3, k=330 + Nq)
+    for with_ref in (True, False):
+        ref = oracle_vs(oracle_mod, w, with_ref=with_ref)
+        e = err(host(run_rhs(sv, w, with_ref=with_ref)), ref)
+        assert e.max() <= TOL64, (Nq, with_ref, e)
+        base = np.random.default_rng(Nq).standard_normal(w.q.shape)
+        out = dev(base.copy())
+        run_rhs(sv, w, with_ref=with_ref, out=out, accumulate=True)
+        assert err(host(out), base + ref).max() <= TOL64, (Nq, with_ref)
+        ref32 = oracle_vs(oracle_mod, w, with_ref=with_ref, fp32=True)
+        e32 = err(host(run_rhs(sv, w, with_ref=with_ref, fp32=True)), ref32)
+        assert e32.max() <= TOL32, (Nq, with_ref, e32)
+        b32 = base.astype(np.float32)
+        out32 = dev(b32.copy())
+        run_rhs(sv, w, with_ref=with_ref, out=out32, accumulate=True, fp32=True)
+        assert err(host(out32), b32.astype(np.float64) + ref32).max() <= TOL32, (Nq, with_ref)
+
+
+@pytest.mark.parametrize("Nq", [3, 8])
+def test_rhs_boundary_faces(sv, oracle_mod, Nq):
+    """A sub-mesh of the box with boundary faces (neighbours outside it, and
+    indices beyond Ne or below -1): those faces add nothing, as in the
+    oracle; the kernel reads nothing through them."""
+    w = I.warped_workload(N=Nq - 1, n_side=4, n_elements=37, k=340 + Nq)
+    nbr = w.nbr.copy()
+    nbr[3, 1] = w.Ne + 5
+    nbr[7, 4] = 2 ** 31 - 1
+    nbr[11, 2] = -7
+    assert (nbr < 0).any()
+    assert err(host(run_rhs(sv, w, nbr=nbr)), oracle_vs(oracle_mod, w, nbr=nbr)).max() <= TOL64
+    ref32 = oracle_vs(oracle_mod, w, nbr=nbr, fp32=True)
+    assert err(host(run_rhs(sv, w, nbr=nbr, fp32=True)), ref32).max() <= TOL32
+    none = np.full_like(w.nbr, -1)
+    got = host(run_rhs(sv, w, nbr=none))
+    v = host(sv.volume_rhs(dev(w.q), dev(w.geo), dev(w.D), dev(w.rho_ref), dev(w.theta_ref),
+                           w.phys.as_tuple()))
+    assert err(got, v).max() <= TOL64
+
+
+def test_rhs_conservative(sv, oracle_mod):
+    """The GLL quadrature of J (v + s) over the periodic box vanishes (no
+    gravity), for the one-launch rate as for the oracle's."""
+    N = 4
+    w = I.warped_workload(N=N, n_side=4, k=342)
+    phys = (I.P0, I.GAMMA, I.R_GAS, 0.0)
+    got = host(sv.rhs(dev(w.q), dev(w.geo), dev(w.D), dev(w.nbr), dev(w.rho_ref),
+                      dev(w.theta_ref), phys))
+    wq = I.gll_weights(N)
+    Nq = N + 1
+    m = np.arange(Nq ** 3)
+    W = (wq[m % Nq] * wq[(m // Nq) % Nq] * wq[m // (Nq * Nq)])[None, :] / w.geo[:, 9]
+    tot = np.einsum("em,ebm->b", W, got)
+    scale = np.einsum("em,ebm->b", W, np.abs(got))
+    assert np.all(np.abs(tot) <= 1e-13 * scale), tot / scale
+
+
+@pytest.mark.slow
+def test_rhs_full_n7_32768(sv, oracle_mod, c2):
+    """v + s at N = 7 on the whole periodic warped 32^3 box, FP64 and FP32, in
+    the launch the benchmark times."""
+    ref = oracle_vs(oracle_mod, c2)
+    e = err(host(run_rhs(sv, c2)), ref)
+    print("rhs N=7 32768 fp64 err", e)
+    assert e.max() <= TOL64
+    ref32 = oracle_vs(oracle_mod, c2, fp32=True)
+    e32 = err(host(run_rhs(sv, c2, fp32=True)), ref32)
+    print("rhs N=7 32768 fp32 err", e32)
+    assert e32.max() <= TOL32
