@@ -355,6 +355,33 @@ sem_status sem_plan_describe(sem_plan plan, char* buf, int32_t len);
 sem_status sem_plan_destroy(sem_plan plan);
 
 /* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * mixed-order batch of sem_batch_plan + sem_batch_execute in one call that
+ * allocates nothing.
+ *
+ * rhs of every block = v(q) (overwrite), evaluated with the built-in tile
+ * shapes (those of sem_batch_plan without SEM_PLAN_AUTOTUNE; the results are
+ * the same bit for bit).  Enqueues two kernel launches on `stream`: one that
+ * writes the tile and block tables into a device array of the library
+ * (SEM_STATIC_MAX_BLOCKS block descriptors and SEM_STATIC_MAX_TILES tiles,
+ * 770 KiB, held on each GPU the library runs on until the process ends), and
+ * the batch kernel.  No hipMalloc, hipFree, copy or memset; nothing to reset
+ * between calls (the tables are rewritten by every call).
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (on different streams, or from several threads without ordering) race.
+ * Blocks, layouts and checks as for sem_batch_plan; the caller keeps the
+ * arrays alive until the launch has run.
+ * Errors: as sem_batch_plan, plus nblocks > SEM_STATIC_MAX_BLOCKS or more than
+ * SEM_STATIC_MAX_TILES tiles -> SEM_ERR_INVALID_ARG.
+ * ------------------------------------------------------------------------- */
+#define SEM_STATIC_MAX_BLOCKS 16
+#define SEM_STATIC_MAX_TILES 32768
+
+sem_status sem_batch_rhs_static(const sem_block* blocks, int32_t nblocks, sem_dtype dtype,
+                                const sem_phys* phys, void* stream);
+
+/* ---------------------------------------------------------------------------
  * One SSP-RK3 (Shu-Osher) step of dq/dt = v(q) (explicit time integration of
  * the method-of-lines rate, Sec. 2), captured once in a HIP graph:
  *   q1 = q + dt v(q);  q2 = 3/4 q + 1/4 (q1 + dt v(q1));

@@ -10,5 +10,5 @@ from .semvol import (  # noqa: F401
     SemError, VolumeRHS, BatchPlan, RK3Graph, axpby, lib, set_max_workgroups, tile_options,
     version, volume_rhs,
     volume_rhs_adjoint, volume_rhs_ext, volume_rhs_affine, volume_rhs_ladder, LADDER_LEVELS,
-    surface_rhs, rhs,
+    surface_rhs, batch_rhs_static, rhs,
 )

@@ -25,7 +25,7 @@ ARCH = "gfx950"
 SOURCES = [
     "ext_f64.hip", "ext_f32.hip", "ladder.hip", "surface_f64.hip", "surface_f32.hip",
     "rhs_f64.hip", "rhs_f32.hip",
-    "batch_f64.hip", "batch_f32.hip",
+    "batch_f64.hip", "batch_f32.hip", "batch_static.hip",
     "kernels_f64.hip", "kernels_f32.hip",
     "sem_api.cpp", "sem_plan.cpp",
 ]

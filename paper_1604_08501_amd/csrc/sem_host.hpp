@@ -35,6 +35,10 @@ struct DefaultTile {
 };
 DefaultTile default_tile(sem_dtype dt, int nq);
 
+// Built-in batch shape of order nq in a launch of nt threads (the shape a
+// plan takes without autotuning); false if none fits.
+bool batch_default_shape(sem_dtype dt, int nt, int nq, int* epb, int* lay);
+
 sem_status check_dtype(sem_dtype dt);
 sem_status check_order(int32_t Ne, int32_t Nq);
 sem_status check_ptr(const void* p, size_t align, const char* name, bool required = true);

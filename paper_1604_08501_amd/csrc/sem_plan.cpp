@@ -534,6 +534,15 @@ sem_status default_shapes(PlanCore& p)
     return fail(SEM_ERR_UNSUPPORTED, "no default batch shape covers every order of the plan");
 }
 
+}  // namespace
+
+bool semapi::batch_default_shape(sem_dtype dt, int nt, int nq, int* epb, int* lay)
+{
+    return default_shape(dt, nt, nq, false, epb, lay);
+}
+
+namespace {
+
 sem_status build_plan(const sem_block* blocks, int32_t nblocks, sem_dtype dt, const sem_phys* phys,
                       uint32_t flags, hipStream_t s, const PlanCore* template_plan,
                       const semk::RkStage* rk, const void* const* rk_x, PlanCore** out)

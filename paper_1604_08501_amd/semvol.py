@@ -36,7 +36,7 @@ EXPORTS = (
     "sem_axpby", "sem_batch_plan", "sem_batch_execute",
     "sem_plan_describe", "sem_plan_destroy", "sem_rk3_graph_create", "sem_rk3_graph_launch",
     "sem_rk3_graph_describe", "sem_rk3_graph_destroy", "sem_set_max_workgroups",
-    "sem_surface_rhs", "sem_rhs",
+    "sem_surface_rhs", "sem_batch_rhs_static", "sem_rhs",
 )
 
 
@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
         "sem_rk3_graph_destroy": ([vp], i32),
         "sem_set_max_workgroups": ([i64], i32),
         "sem_surface_rhs": ([i32, i32, i32, vp, vp, vp, vp, P(sem_phys), vp, i32, vp], i32),
+        "sem_batch_rhs_static": ([P(sem_block), i32, i32, P(sem_phys), vp], i32),
         "sem_rhs": ([i32, i32, i32, vp, vp, vp, vp, vp, vp, P(sem_phys), vp, i32, vp], i32),
     }
     for name, (args, res) in sig.items():
@@ -411,6 +412,17 @@ class BatchPlan:
             self.close()
         except Exception:
             pass
+
+
+def batch_rhs_static(blocks: Sequence[dict], phys=None, stream=None) -> None:
+    """The mixed-order batch of ``BatchPlan(blocks).execute()`` (built-in
+    tile shapes) in one call that allocates no device memory; ``blocks`` as
+    for ``BatchPlan``, every block's ``rhs`` overwritten."""
+    dtype = blocks[0]["q"].dtype
+    arr, _ = _blocks(blocks, dtype)
+    ph = _phys(phys)
+    _check(lib().sem_batch_rhs_static(arr, len(blocks), _code(dtype), ctypes.byref(ph),
+                                      _stream(stream)))
 
 
 class RK3Graph:

@@ -131,6 +131,35 @@ def test_batch_plan_validation(L, sv):
     assert L.sem_plan_describe(None, buf, 16) == -1
 
 
+def test_batch_rhs_static_validation(L, sv):
+    """The entry point without allocation rejects, on the host, what the plan
+    rejects and what exceeds its static tables (more than 16 blocks, more
+    than 32768 tiles)."""
+    ph = sv.sem_phys(1e5, 1.4, 287.0, 9.81)
+    blocks = (sv.sem_block * 17)()
+    for i in range(17):
+        base = (i + 1) << 40
+        blocks[i] = sv.sem_block(5, 10, base, base + (1 << 36), base + (2 << 36), None, None,
+                                 base + (3 << 36))
+    assert L.sem_batch_rhs_static(blocks, 0, 0, ctypes.byref(ph), None) == -1
+    assert L.sem_batch_rhs_static(blocks, 17, 0, ctypes.byref(ph), None) == -1
+    assert b"16 blocks" in L.sem_last_error()
+    assert L.sem_batch_rhs_static(blocks, 2, 0, None, None) == -1
+    assert L.sem_batch_rhs_static(blocks, 2, 5, ctypes.byref(ph), None) == -1
+    blocks[1] = sv.sem_block(13, 10, A, 2 * A, 3 * A, None, None, 4 * A)     # Nq not compiled
+    assert L.sem_batch_rhs_static(blocks, 2, 0, ctypes.byref(ph), None) == -2
+    assert b"block 1" in L.sem_last_error()
+    # 40000 elements at Nq = 10 are 40000 one-element tiles
+    b = 1 << 44
+    big = (sv.sem_block * 1)(sv.sem_block(10, 40000, b, b + (1 << 40), b + (2 << 40), None, None,
+                                          b + (3 << 40)))
+    assert L.sem_batch_rhs_static(big, 1, 0, ctypes.byref(ph), None) == -1
+    assert b"static tile table" in L.sem_last_error()
+    # rhs overlapping q
+    bad = (sv.sem_block * 1)(sv.sem_block(5, 10, A, 2 * A, 3 * A, None, None, 3 * A + 16))
+    assert L.sem_batch_rhs_static(bad, 1, 0, ctypes.byref(ph), None) == -1
+
+
 def test_rk3_validation(L, sv):
     ph = sv.sem_phys(1e5, 1.4, 287.0, 9.81)
     out = ctypes.c_void_p()

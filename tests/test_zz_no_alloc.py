@@ -1,0 +1,58 @@
+"""The mixed-order batch entry point that allocates nothing
+(sem_batch_rhs_static) against the plan-based one (sem_batch_plan +
+sem_batch_execute, built-in tile shapes) through the C-ABI: the same values
+bit for bit, and both within the forward gates of the oracle (FP64 1e-12,
+FP32 2e-5 on the rounded inputs).  Two calls in a row, the second with fewer
+blocks and elements, so the second runs on tables left by the first."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1604_08501_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 2e-5
+
+
+@pytest.fixture(scope="module")
+def sv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1604_08501_amd as m
+    m.lib()
+    return m
+
+
+def _blocks(ws, dtype):
+    cast = (lambda a: a) if dtype == torch.float64 else (lambda a: np.asarray(a, np.float32))
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return [dict(q=dev(cast(w.q)), geo=dev(cast(w.geo)), D=dev(cast(w.D)),
+                 rho_ref=dev(cast(w.rho_ref)), theta_ref=dev(w.theta_ref),
+                 rhs=torch.full(w.q.shape, float("nan"), dtype=dtype, device="cuda"))
+            for w in ws]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batch_rhs_static_matches_plan(sv, oracle_mod, dtype):
+    tol = TOL64 if dtype == torch.float64 else TOL32
+    for orders, per_order, k in (((1, 3, 5, 7, 9), 61, 400), ((2, 4), 9, 401)):
+        ws = I.mixed_order_workloads(orders=orders, per_order=per_order, k=k)
+        phys = ws[0].phys.as_tuple()
+        blocks = _blocks(ws, dtype)
+        plan = sv.BatchPlan(blocks, phys)
+        plan.execute()
+        torch.cuda.synchronize()
+        ref = [b["rhs"].cpu().numpy().copy() for b in blocks]
+        plan.close()
+        for b in blocks:
+            b["rhs"].fill_(float("nan"))
+        sv.batch_rhs_static(blocks, phys)
+        torch.cuda.synchronize()
+        for w, b, r in zip(ws, blocks, ref):
+            got = b["rhs"].cpu().numpy()
+            assert np.array_equal(got, r), (orders, w.N)
+            src = w if dtype == torch.float64 else I.upcast(I.to_fp32(w))
+            o = oracle_mod.volume_rhs(src.D, src.geo, src.q, src.rho_ref, src.theta_ref, phys)
+            e = I.rel_err_per_field(got, o)
+            assert e.max() <= tol, (orders, w.N, e)
