@@ -69,7 +69,12 @@ typedef enum sem_status {
     SEM_ERR_NO_MEMORY = -4      /* host or device allocation failed (plans, graphs) */
 } sem_status;
 
-typedef enum sem_dtype { SEM_F64 = 0, SEM_F32 = 1 } sem_dtype;
+/* Element type of the arrays.  An int32_t rather than an enum, so that any
+ * value a caller passes is well defined inside the library and rejected with
+ * SEM_ERR_INVALID_ARG unless it is one of these. */
+typedef int32_t sem_dtype;
+#define SEM_F64 0
+#define SEM_F32 1
 
 /* Physical constants: the paper's kernel arguments p_p0, p_Gamma, p_R
  * (reference pressure, ratio of specific heats, gas constant), plus the

@@ -27,7 +27,7 @@ SOURCES = [
     "rhs_f64.hip", "rhs_f32.hip",
     "batch_f64.hip", "batch_f32.hip", "batch_static.hip",
     "kernels_f64.hip", "kernels_f32.hip",
-    "sem_api.cpp", "sem_plan.cpp",
+    "sem_api.cpp", "sem_plan.cpp", "sem_cache.cpp",
 ]
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

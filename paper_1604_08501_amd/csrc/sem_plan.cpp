@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "sem.h"
+#include "sem_cache.hpp"
 #include "sem_host.hpp"
 #include "sem_internal.hpp"
 
@@ -229,17 +230,11 @@ sem_status finalize(PlanCore& p, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// Plan cache: a flat JSON object {"key": {"epb": E, "layout": L, "us": T}} in
+// Plan cache (file format in sem_cache.cpp): a flat JSON object in
 // the file named by SEM_PLAN_CACHE, keyed by device arch, dtype, workgroup
 // size, the LDS cap of the launch, Nq and a power-of-two element bucket.
 // ---------------------------------------------------------------------------
 std::mutex g_cache_mu;
-
-struct CacheEntry {
-    int epb = 0;
-    int lay = 0;
-    double us = -1.0;
-};
 
 std::string cache_path()
 {
@@ -267,71 +262,6 @@ std::string cache_key(const std::string& arch, sem_dtype dt, bool rk, int nt, in
     snprintf(buf, sizeof buf, "%s/%s%s/nt%d/lds%d/nq%d/ne%lld", arch.c_str(),
              dt == SEM_F64 ? "f64" : "f32", rk ? "-rk" : "", nt, cap, nq, (long long)bucket);
     return buf;
-}
-
-double json_number(const std::string& body, const char* name, double dflt)
-{
-    const std::string key = std::string("\"") + name + "\"";
-    size_t k = body.find(key);
-    if (k == std::string::npos)
-        return dflt;
-    size_t c = body.find(':', k);
-    if (c == std::string::npos)
-        return dflt;
-    return atof(body.c_str() + c + 1);
-}
-
-std::map<std::string, CacheEntry> cache_read(const std::string& path)
-{
-    std::map<std::string, CacheEntry> m;
-    FILE* f = fopen(path.c_str(), "rb");
-    if (!f)
-        return m;
-    std::string s;
-    char buf[4096];
-    size_t n;
-    while ((n = fread(buf, 1, sizeof buf, f)) > 0)
-        s.append(buf, n);
-    fclose(f);
-    size_t pos = 0;
-    while (true) {
-        size_t k0 = s.find('"', pos);
-        if (k0 == std::string::npos)
-            break;
-        size_t k1 = s.find('"', k0 + 1);
-        if (k1 == std::string::npos)
-            break;
-        std::string key = s.substr(k0 + 1, k1 - k0 - 1);
-        size_t ob = s.find('{', k1);
-        size_t cb = s.find('}', k1);
-        if (ob == std::string::npos || cb == std::string::npos || cb < ob)
-            break;
-        std::string body = s.substr(ob, cb - ob);
-        CacheEntry e;
-        e.epb = (int)json_number(body, "epb", 0);
-        e.lay = (int)json_number(body, "layout", 0);
-        e.us = json_number(body, "us", -1.0);
-        if (e.epb > 0)
-            m[key] = e;
-        pos = cb + 1;
-    }
-    return m;
-}
-
-void cache_write(const std::string& path, const std::map<std::string, CacheEntry>& m)
-{
-    std::string tmp = path + ".tmp";
-    FILE* f = fopen(tmp.c_str(), "wb");
-    if (!f)
-        return;
-    fprintf(f, "{\n");
-    size_t i = 0;
-    for (const auto& kv : m)
-        fprintf(f, "  \"%s\": {\"epb\": %d, \"layout\": %d, \"us\": %.3f}%s\n", kv.first.c_str(),
-                kv.second.epb, kv.second.lay, kv.second.us, ++i < m.size() ? "," : "");
-    fprintf(f, "}\n");
-    fclose(f);
-    rename(tmp.c_str(), path.c_str());
 }
 
 // Time one order's blocks alone with the shape currently in p.orders, under
@@ -387,10 +317,10 @@ sem_status autotune(PlanCore& p, bool use_cache, hipStream_t s)
 {
     const std::string arch = arch_name(p.device);
     const std::string path = use_cache ? cache_path() : std::string();
-    std::map<std::string, CacheEntry> cache;
+    std::map<std::string, semcache::Entry> cache;
     if (!path.empty()) {
         std::lock_guard<std::mutex> lk(g_cache_mu);
-        cache = cache_read(path);
+        cache = semcache::read(path);
     }
     SEM_TRY(upload_blocks(p, s));
     bool all_cached = true;
@@ -469,7 +399,7 @@ sem_status autotune(PlanCore& p, bool use_cache, hipStream_t s)
                 oc.lay = best_lay;
                 oc.us = best;
                 total += best;
-                cache[key] = CacheEntry{best_epb, best_lay, best};
+                cache[key] = semcache::Entry{best_epb, best_lay, best};
             }
             if (feasible && total < best_total) {
                 best_total = total;
@@ -487,10 +417,10 @@ sem_status autotune(PlanCore& p, bool use_cache, hipStream_t s)
     p.from_cache = all_cached;
     if (!path.empty() && !all_cached) {
         std::lock_guard<std::mutex> lk(g_cache_mu);
-        auto merged = cache_read(path);
+        auto merged = semcache::read(path);
         for (auto& kv : cache)
             merged[kv.first] = kv.second;
-        cache_write(path, merged);
+        semcache::write(path, merged);
     }
     if (log_enabled())
         fprintf(stderr, "[semvol] autotune chose nt=%d, LDS cap %d B (sum of per-order times %.2f us)%s\n",
