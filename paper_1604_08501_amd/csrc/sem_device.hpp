@@ -541,10 +541,15 @@ __device__ __forceinline__ int64_t xcd_contiguous_block(int64_t b, int64_t G)
 // and the sound speed sqrt(gamma p / rho) of the full pressure.
 constexpr int kFaceVals = 7;
 
+// Values staged per own face node by its owner: the state (5), the flux
+// pressure, the sound speed, the outward normal times its area factor (3)
+// and 1/rho.
+constexpr int kOwnVals = 11;
+
 template <int NQ>
 constexpr int face_lds_values_per_element()
 {
-    return 6 * kFaceVals * NQ * NQ;
+    return 6 * (kFaceVals + kOwnVals) * NQ * NQ;
 }
 
 // Node of face (d, side) with tangential indices (a2, b2).
@@ -601,23 +606,103 @@ __device__ __forceinline__ void stage_neighbour_faces(const BlockPtrs<T>& B,
     }
 }
 
-// acc[b] += (1/w_N) sum over the node's faces of (F*_b - Fn_b(q-)), so that
-// the epilogue's -(1/J) acc + source is v + s.  st: the node's own state and
-// full pressure; (i, j, k): its indices; nb: the element's six neighbour
-// indices; sFe: the element's staged neighbour faces.
+// The owner of a boundary node stages, for each face of the element the node
+// lies on, the node's state, flux pressure, sound speed, outward normal N
+// (sigma (g_0d, g_1d, g_2d) at the node) and 1/rho in sOwn[f][v][a].
 template <typename T, int NQ>
-__device__ __forceinline__ void add_face_terms(const NodeState<T, 5>& st, int i, int j, int k,
-                                               const int32_t* __restrict__ nb, int64_t Ne,
-                                               const T* __restrict__ sFe, T gam, T lift,
-                                               T (&acc)[5])
+__device__ __forceinline__ void stage_own_faces(const NodeState<T, 5>& st, int i, int j, int k,
+                                                T gam, T* __restrict__ sOwn)
 {
     constexpr int NQ2 = NQ * NQ;
     constexpr int N = NQ - 1;
     const int ijk[3] = {i, j, k};
     if (!(i == 0 || i == N || j == 0 || j == N || k == 0 || k == N))
         return;
-    const T cm = sqrt(gam * st.pfull * st.rinv);
-    const T qm[5] = {st.rho, st.U1, st.U2, st.U3, st.Th};
+    const T c = sqrt(gam * st.pfull * st.rinv);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int id = ijk[d];
+        if (id != 0 && id != N)
+            continue;
+        const int side = id == N ? 1 : 0;
+        const int a = d == 0 ? j + NQ * k : (d == 1 ? i + NQ * k : i + NQ * j);
+        const T sg = side ? (T)1 : (T)-1;
+        const T v[kOwnVals] = {st.rho, st.U1, st.U2, st.U3, st.Th, st.pp, c,
+                               sg * st.g[3 * d], sg * st.g[3 * d + 1], sg * st.g[3 * d + 2],
+                               st.rinv};
+        T* __restrict__ o = sOwn + (2 * d + side) * (kOwnVals * NQ2) + a;
+#pragma unroll
+        for (int b = 0; b < kOwnVals; ++b)
+            o[b * NQ2] = v[b];
+    }
+}
+
+// One thread per face node of the tile: F* - Fn(q-) of the five fields from
+// the staged own and neighbour values, written over the neighbour's state in
+// sFace (zero for a boundary face).
+template <typename T, int NQ, int EPB, int NT>
+__device__ __forceinline__ void face_fluxes(const int32_t* __restrict__ nbr, int64_t Ne, int64_t e0,
+                                            int ne, T* __restrict__ sFace,
+                                            const T* __restrict__ sOwn)
+{
+    constexpr int NQ2 = NQ * NQ;
+    constexpr int PER = 6 * NQ2;
+#pragma unroll 1
+    for (int x = threadIdx.x; x < EPB * PER; x += NT) {
+        const int es = x / PER;
+        const int r = x - es * PER;
+        const int f = r / NQ2;
+        const int a = r - f * NQ2;
+        if (es >= ne)
+            continue;
+        T* __restrict__ v = sFace + es * (kFaceVals * PER) + f * (kFaceVals * NQ2) + a;
+        const int64_t en = nbr[(e0 + es) * 6 + f];
+        if (en < 0 || en >= Ne) {
+#pragma unroll
+            for (int b = 0; b < 5; ++b)
+                v[b * NQ2] = (T)0;   // boundary face: exterior state = interior state
+            continue;
+        }
+        const T* __restrict__ o = sOwn + es * (kOwnVals * PER) + f * (kOwnVals * NQ2) + a;
+        T qm[5], qp[5];
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+            qm[b] = o[b * NQ2];
+            qp[b] = v[b * NQ2];
+        }
+        const T pm = o[5 * NQ2], cm = o[6 * NQ2];
+        const T n0 = o[7 * NQ2], n1 = o[8 * NQ2], n2 = o[9 * NQ2], rinv_m = o[10 * NQ2];
+        const T pp = v[5 * NQ2], cp = v[6 * NQ2];
+        const T nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+        const T rinv_p = (T)1 / qp[0];
+        const T NUm = n0 * qm[1] + n1 * qm[2] + n2 * qm[3];
+        const T NUp = n0 * qp[1] + n1 * qp[2] + n2 * qp[3];
+        const T vm = NUm * rinv_m, vp = NUp * rinv_p;   // N . u on each side
+        const T lam_m = fabs(vm) / nn + cm;
+        const T lam_p = fabs(vp) / nn + cp;
+        const T diss = (T)0.5 * (lam_m > lam_p ? lam_m : lam_p) * nn;
+        const T dp = pp - pm;
+        const T dF[5] = {NUp - NUm, qp[1] * vp - qm[1] * vm + n0 * dp,
+                         qp[2] * vp - qm[2] * vm + n1 * dp, qp[3] * vp - qm[3] * vm + n2 * dp,
+                         qp[4] * vp - qm[4] * vm};
+#pragma unroll
+        for (int b = 0; b < 5; ++b)
+            v[b * NQ2] = (T)0.5 * dF[b] - diss * (qp[b] - qm[b]);
+    }
+}
+
+// acc[b] += (1/w_N) sum over the node's faces of (F* - Fn(q-))_b, so that the
+// epilogue's -(1/J) acc + source is v + s; faces visited r, s, t in order.
+// sFe: the element's face results, VALS values per face node slot.
+template <typename T, int NQ, int VALS = kFaceVals>
+__device__ __forceinline__ void gather_face_terms(int i, int j, int k,
+                                                  const T* __restrict__ sFe, T lift, T (&acc)[5])
+{
+    constexpr int NQ2 = NQ * NQ;
+    constexpr int N = NQ - 1;
+    const int ijk[3] = {i, j, k};
+    if (!(i == 0 || i == N || j == 0 || j == N || k == 0 || k == N))
+        return;
     T sacc[5] = {(T)0, (T)0, (T)0, (T)0, (T)0};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -625,33 +710,11 @@ __device__ __forceinline__ void add_face_terms(const NodeState<T, 5>& st, int i,
         if (id != 0 && id != N)
             continue;
         const int side = id == N ? 1 : 0;
-        const int64_t en = nb[2 * d + side];
-        if (en < 0 || en >= Ne)
-            continue;   // boundary face: exterior state = interior state
         const int a = d == 0 ? j + NQ * k : (d == 1 ? i + NQ * k : i + NQ * j);
-        const T* __restrict__ v = sFe + (2 * d + side) * (kFaceVals * NQ2) + a;
-        T qp[5];
+        const T* __restrict__ v = sFe + (2 * d + side) * (VALS * NQ2) + a;
 #pragma unroll
         for (int b = 0; b < 5; ++b)
-            qp[b] = v[b * NQ2];
-        const T pp_flux = v[5 * NQ2], cp = v[6 * NQ2];
-        const T sg = side ? (T)1 : (T)-1;
-        const T n0 = sg * st.g[3 * d], n1 = sg * st.g[3 * d + 1], n2 = sg * st.g[3 * d + 2];
-        const T nn = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
-        const T rinv_p = (T)1 / qp[0];
-        const T NUm = n0 * qm[1] + n1 * qm[2] + n2 * qm[3];
-        const T NUp = n0 * qp[1] + n1 * qp[2] + n2 * qp[3];
-        const T vm = NUm * st.rinv, vp = NUp * rinv_p;   // N . u on each side
-        const T lam_m = fabs(vm) / nn + cm;
-        const T lam_p = fabs(vp) / nn + cp;
-        const T diss = (T)0.5 * (lam_m > lam_p ? lam_m : lam_p) * nn;
-        const T dp = pp_flux - st.pp;
-        const T dF[5] = {NUp - NUm, qp[1] * vp - qm[1] * vm + n0 * dp,
-                         qp[2] * vp - qm[2] * vm + n1 * dp, qp[3] * vp - qm[3] * vm + n2 * dp,
-                         qp[4] * vp - qm[4] * vm};
-#pragma unroll
-        for (int b = 0; b < 5; ++b)
-            sacc[b] += (T)0.5 * dF[b] - diss * (qp[b] - qm[b]);
+            sacc[b] += v[b * NQ2];
     }
 #pragma unroll
     for (int b = 0; b < 5; ++b)
@@ -664,7 +727,8 @@ template <typename T>
 struct SurfIn {
     const int32_t* nbr;
     T lift;
-    T* sFace;
+    T* sFace;   // [EPB][6][kFaceVals][Nq^2]: neighbour values, then F* - Fn(q-)
+    T* sOwn;    // [EPB][6][kOwnVals][Nq^2]: the element's own face values
 };
 
 // ---------------------------------------------------------------------------
@@ -824,8 +888,18 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
             rn[p].load(B, rk, e0 + es, t - es * M, M, st[p]);
         }
     }
-    if constexpr (SURF)
+    if constexpr (SURF) {
         stage_neighbour_faces<T, NQ, EPB, NT>(B, sv.nbr, ph, e0, ne, sv.sFace);
+#pragma unroll
+        for (int p = 0; p < NPT; ++p)
+            if (live[p]) {
+                const int t = tid + p * NT;
+                const int es = t / M;
+                const int m = t - es * M;
+                stage_own_faces<T, NQ>(st[p], m % NQ, (m / NQ) % NQ, m / NQ2, (T)ph.gamma,
+                                       sv.sOwn + es * (kOwnVals * 6 * NQ2));
+            }
+    }
     if constexpr (RREG) {
 #pragma unroll
         for (int p = 0; p < NPT; ++p)
@@ -860,6 +934,11 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
                                                 m / NQ2, acc[p]);
             }
     }
+    if constexpr (SURF) {
+        // the staged faces were written before the first direction's barrier
+        face_fluxes<T, NQ, EPB, NT>(sv.nbr, B.Ne, e0, ne, sv.sFace, sv.sOwn);
+        __syncthreads();
+    }
 #pragma unroll
     for (int p = 0; p < NPT; ++p)
         if (live[p]) {
@@ -867,9 +946,8 @@ __device__ __forceinline__ void volume_tile_alias(const BlockPtrs<T>& B, int64_t
             const int es = t / M;
             if constexpr (SURF) {
                 const int m = t - es * M;
-                add_face_terms<T, NQ>(st[p], m % NQ, (m / NQ) % NQ, m / NQ2, sv.nbr + (e0 + es) * 6,
-                                      B.Ne, sv.sFace + es * face_lds_values_per_element<NQ>(),
-                                      (T)ph.gamma, sv.lift, acc[p]);
+                gather_face_terms<T, NQ>(m % NQ, (m / NQ) % NQ, m / NQ2,
+                                         sv.sFace + es * (kFaceVals * 6 * NQ2), sv.lift, acc[p]);
             }
             store_node<T, M, NF, ACC, RK>(B, rk, e0 + es, t - es * M, acc[p], st[p].jinv,
                                           st[p].src, rn[p]);
