@@ -56,9 +56,12 @@ def flops_per_node(Nq: int) -> int:
 
 
 # Sources that define the kernels whose measured traffic is recorded (the
-# single-order volume and adjoint kernels and the extended kernels).
+# single-order volume and adjoint kernels, the extended kernels, the surface
+# kernel and the whole-rate kernel).
 VOLUME_KERNEL_SOURCES = ("sem_device.hpp", "sem_internal.hpp", "kernels.inc", "kernels_f64.hip",
-                         "kernels_f32.hip", "ext.inc", "ext_f64.hip", "ext_f32.hip")
+                         "kernels_f32.hip", "ext.inc", "ext_f64.hip", "ext_f32.hip",
+                         "surface.inc", "surface_f64.hip", "surface_f32.hip", "rhs.inc",
+                         "rhs_f64.hip", "rhs_f32.hip")
 
 
 def kernel_source_hash() -> str:
@@ -81,6 +84,13 @@ def measured_traffic(kernel_key: str):
         return None
     ent = d.get("kernels", {}).get(kernel_key)
     return ent.get("bytes_per_launch") if ent else None
+
+
+def roof(gbs: float, key: str) -> dict:
+    """Roofline record of one leg: its algorithmic GB/s against the HBM peak,
+    and the HBM bytes per launch measured by PMC counters (or None)."""
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(key)}
 
 
 # The paper's timing method (Sec. 4): after warm-up, keep launching for at
@@ -199,8 +209,9 @@ def bench_adjoint(sv, I, steps: int, warmup: int, stream):
             lambda: sv.volume_rhs_adjoint(q, geo, D, lam, w.phys.as_tuple(), out=mu),
             steps, warmup, stream)
         esz = 8 if tag == "f64" else 4
-        out[tag] = {"ms": ms, "el_s": w.Ne / (ms * 1e-3),
-                    "GBs": 25 * esz * nodes / (ms * 1e-3) / 1e9}
+        gbs = 25 * esz * nodes / (ms * 1e-3) / 1e9
+        out[tag] = {"ms": ms, "el_s": w.Ne / (ms * 1e-3), "GBs": gbs,
+                    "roofline": roof(gbs, f"adjoint_{tag}_n7")}
     return out
 
 
@@ -238,8 +249,9 @@ def bench_paper_table2(sv, I, steps: int, warmup: int, stream):
             # per node: q 8 + metric terms of the used directions and 1/J read,
             # rhs 8 read and 8 written, 4 bytes each
             byt = (8 + geo_words + 16) * 4 * nodes
-            row[name] = {"ms": ms, "el_s": w.Ne / (ms * 1e-3), "GBs": byt / (ms * 1e-3) / 1e9,
-                         "bytes": byt}
+            gbs = byt / (ms * 1e-3) / 1e9
+            row[name] = {"ms": ms, "el_s": w.Ne / (ms * 1e-3), "GBs": gbs, "bytes": byt,
+                         "roofline": roof(gbs, f"table2_{name}_nq{Nq}")}
         row["speedup_rs_vs_fury_x"] = PAPER_TABLE2_MS[Nq]["R9 Fury X"] / row["rs"]["ms"]
         out[f"Nq{Nq}"] = row
         del q, geo, D, rhs
@@ -312,10 +324,11 @@ benchmark kernel (levels 1-6) at Nq = 8 on the Table 2 shape.
         # per node: q 5 + rho_ref read, rhs 5 written (dtype) + theta_ref (FP64);
         # per element: 10 metric words
         byt = (11 * esz + 8) * nodes + 10 * esz * w.Ne
+        gbs = byt / (ms_elem * 1e-3) / 1e9
         out[tag] = {"per_element_ms": ms_elem, "per_node_ms": ms_node,
-                    "el_s": w.Ne / (ms_elem * 1e-3), "GBs": byt / (ms_elem * 1e-3) / 1e9,
+                    "el_s": w.Ne / (ms_elem * 1e-3), "GBs": gbs,
                     "bytes": byt, "speedup_vs_per_node": ms_node / ms_elem,
-                    "max_rel_diff_vs_per_node": diff}
+                    "max_rel_diff_vs_per_node": diff, "roofline": roof(gbs, f"affine_{tag}_n7")}
         del q, geo, D, rr, tr, g_el, o1, o2
         torch.cuda.empty_cache()
     return out
@@ -372,15 +385,12 @@ def bench_surface(sv, I, w, steps: int, warmup: int, stream):
         gbs_one = bpe_one * Ne / (ms_one * 1e-3) / 1e9
         out["bytes_per_element"][tag] = bpe
         out[tag] = {"ms": ms, "median_ms": med, "el_s": Ne / (ms * 1e-3), "GBs": gbs,
-                    "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS,
-                                 "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS},
+                    "roofline": roof(gbs, f"surface_{tag}_n7"),
                     "volume_plus_surface_ms": ms_full,
                     "volume_plus_surface_el_s": Ne / (ms_full * 1e-3),
                     "one_launch": {"ms": ms_one, "median_ms": med_one, "el_s": Ne / (ms_one * 1e-3),
                                    "bytes_per_element": bpe_one, "GBs": gbs_one,
-                                   "roofline": {"bound": "hbm", "achieved": gbs_one,
-                                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                                "frac": gbs_one / HBM_PEAK_GBS},
+                                   "roofline": roof(gbs_one, f"rhs_{tag}_n7"),
                                    "speedup_vs_two_launches": ms_full / ms_one}}
         del q, geo, D, rr, tr, nbr, rhs
         torch.cuda.empty_cache()
