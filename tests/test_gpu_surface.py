@@ -236,3 +236,30 @@ def test_rhs_full_n7_32768(sv, oracle_mod, c2):
     e32 = err(host(run_rhs(sv, c2, fp32=True)), ref32)
     print("rhs N=7 32768 fp32 err", e32)
     assert e32.max() <= TOL32
+
+
+def test_rhs_and_surface_inside_a_captured_graph(sv):
+    """sem_rhs and sem_surface_rhs (accumulating) record into a captured HIP
+    graph; every replay, with eager work between replays, equals the eager
+    result bit for bit."""
+    w = I.warped_workload(N=5, n_side=3, k=350)
+    ph = w.phys.as_tuple()
+    q, geo, D, nbr, rr, tr = (dev(a) for a in (w.q, w.geo, w.D, w.nbr, w.rho_ref, w.theta_ref))
+    eager = sv.rhs(q, geo, D, nbr, rr, tr, ph)
+    sv.surface_rhs(q, geo, nbr, tr, ph, out=eager, accumulate=True)
+    out = torch.empty_like(q)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            sv.rhs(q, geo, D, nbr, rr, tr, ph, out=out)
+            sv.surface_rhs(q, geo, nbr, tr, ph, out=out, accumulate=True)
+    torch.cuda.current_stream().wait_stream(s)
+    for replay in range(3):
+        out.fill_(float("nan"))
+        sv.volume_rhs(q, geo, D, rr, tr, ph)           # eager work between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), replay
