@@ -263,3 +263,19 @@ def test_rhs_and_surface_inside_a_captured_graph(sv):
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(out, eager), replay
+
+
+def test_surface_and_rhs_deterministic(sv):
+    """Two launches of the surface pass and of the whole rate give the same
+    bits (each face node's flux is computed by one thread and every node sums
+    its faces in a fixed order)."""
+    w = I.warped_workload(N=7, n_side=4, k=360)
+    ph = w.phys.as_tuple()
+    q, geo, D, nbr, rr, tr = (dev(a) for a in (w.q, w.geo, w.D, w.nbr, w.rho_ref, w.theta_ref))
+    for _ in range(2):
+        a = host(sv.surface_rhs(q, geo, nbr, tr, ph))
+        b = host(sv.surface_rhs(q, geo, nbr, tr, ph))
+        assert np.array_equal(a, b)
+        c = host(sv.rhs(q, geo, D, nbr, rr, tr, ph))
+        d = host(sv.rhs(q, geo, D, nbr, rr, tr, ph))
+        assert np.array_equal(c, d)
