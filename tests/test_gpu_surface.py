@@ -100,6 +100,7 @@ def test_single_element_periodic_onto_itself(sv, oracle_mod):
     w = I.warped_workload(N=5, n_side=1, k=321)
     assert np.all(w.nbr == 0)
     assert err(host(run(sv, w)), oracle_s(oracle_mod, w)).max() <= TOL64
+    assert err(host(run_rhs(sv, w)), oracle_vs(oracle_mod, w)).max() <= TOL64
 
 
 def test_volume_plus_surface_is_conservative(sv, oracle_mod):

@@ -86,3 +86,42 @@ def test_batch_rhs_static_inside_a_captured_graph(sv):
         torch.cuda.synchronize()
         for b, e in zip(blocks, eager):
             assert torch.equal(b["rhs"], e), replay
+
+
+def test_batch_rhs_static_at_the_tile_limit(sv):
+    """Exactly SEM_STATIC_MAX_TILES tiles (32768 tiles of the built-in FP64
+    Nq = 4 shape, 8 elements each): the same bits as the plan-based entry
+    point; one element more is rejected before any launch."""
+    opts = sv.tile_options(torch.float64, 4)
+    plan_probe = sv.BatchPlan(_blocks(I.mixed_order_workloads(orders=(3,), per_order=8, k=404),
+                                      torch.float64), (1e5, 1.4, 287.0, 9.81))
+    epb = plan_probe.describe()["orders"][0]["elems_per_block"]
+    plan_probe.close()
+    assert any(e == epb for e, _ in opts)
+    Ne = 32768 * epb
+    M = 64
+    g = torch.Generator(device="cuda").manual_seed(405)
+    rho = 1.0 + 0.01 * torch.rand(Ne, M, device="cuda", dtype=torch.float64, generator=g)
+    q = torch.stack([rho] + [rho * 10 * (torch.rand(Ne, M, device="cuda", dtype=torch.float64,
+                                                    generator=g) - 0.5) for _ in range(3)]
+                    + [rho * 300.0], dim=1).contiguous()
+    w1 = I.warped_workload(N=3, n_elements=1, k=406)
+    geo = torch.from_numpy(w1.geo).cuda().expand(Ne, 10, M).contiguous()
+    D = torch.from_numpy(w1.D).cuda()
+    phys = w1.phys.as_tuple()
+    blocks = [dict(q=q, geo=geo, D=D, rhs=torch.full_like(q, float("nan")))]
+    plan = sv.BatchPlan(blocks, phys)
+    assert plan.describe()["tiles"] == 32768
+    plan.execute()
+    torch.cuda.synchronize()
+    ref = blocks[0]["rhs"].clone()
+    plan.close()
+    blocks[0]["rhs"].fill_(float("nan"))
+    sv.batch_rhs_static(blocks, phys)
+    torch.cuda.synchronize()
+    assert torch.equal(blocks[0]["rhs"], ref)
+    assert torch.isfinite(ref).all()
+    over = [dict(q=torch.cat([q, q[:1]]), geo=torch.cat([geo, geo[:1]]), D=D,
+                 rhs=torch.empty(Ne + 1, 5, M, dtype=torch.float64, device="cuda"))]
+    with pytest.raises(sv.SemError, match="static tile table"):
+        sv.batch_rhs_static(over, phys)
