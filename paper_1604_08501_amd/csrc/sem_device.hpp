@@ -140,6 +140,18 @@ struct Pressure<float> {
     {
         return expf(g * logf(x));
     }
+    // log(1 + x) by Goldberg's method (Theorem 4 of "What every computer
+    // scientist should know about floating-point arithmetic", 1991): with
+    // u = 1 + x rounded, log(1 + x) = x if u == 1, else log(u) x / (u - 1).
+    // The factor x / (u - 1) undoes the rounding of u, so small x keeps its
+    // digits; with the 1-ulp hardware reciprocal the relative error stays a
+    // few ulp.  It costs a log and a reciprocal, a third of the instructions
+    // of the library log1pf (3.6% of the FP32 volume + surface launch).
+    static __device__ __forceinline__ float log1p_g(float x)
+    {
+        const float u = 1.0f + x;
+        return u == 1.0f ? x : logf(u) * (x * __builtin_amdgcn_rcpf(u - 1.0f));
+    }
     static __device__ __forceinline__ float eval(float Th, bool has_ref, double thr,
                                                  const Phys& ph)
     {
@@ -148,7 +160,7 @@ struct Pressure<float> {
             const float dth = (float)((double)Th - thr);
             const float trf = (float)thr;
             const float pref = p0 * xgamma(s * trf, g);
-            return pref * expm1f(g * log1pf(dth / trf));
+            return pref * expm1f(g * log1p_g(dth / trf));
         }
         return p0 * xgamma(s * Th, g);
     }
@@ -166,7 +178,7 @@ struct Pressure<float> {
             const float dth = (float)((double)Th - thr);
             const float trf = (float)thr;
             const float pref = p0 * xgamma(s * trf, g);
-            pflux = pref * expm1f(g * log1pf(dth / trf));
+            pflux = pref * expm1f(g * log1p_g(dth / trf));
             pfull = pref + pflux;
         } else {
             pfull = pflux = p0 * xgamma(s * Th, g);
