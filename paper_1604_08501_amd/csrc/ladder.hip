@@ -158,6 +158,8 @@ template <int NQ, int LEVEL>
 static hipError_t ladder_one(int64_t Ne, const float* D, const float* geo, const float* q,
                              float* rhs, const semk::Phys& ph, hipStream_t s)
 {
+    if (!dispatch_fits(Ne, semk::ladder_threads<NQ>()))
+        return hipErrorInvalidConfiguration;
     hipLaunchKernelGGL((semk::ladder_kernel<NQ, LEVEL>), dim3((unsigned)Ne),
                        dim3(semk::ladder_threads<NQ>()), 0, s, D, geo, q, rhs, ph);
     return hipGetLastError();

@@ -25,6 +25,13 @@
 
 namespace semh {
 
+// A dispatch's work-item count (workgroups x lanes) is a 32-bit field of the
+// dispatch packet: launches beyond it fail with this error instead.
+inline bool dispatch_fits(int64_t groups, int threads)
+{
+    return groups >= 1 && groups * (int64_t)threads <= (int64_t)UINT32_MAX;
+}
+
 struct VariantDef {
     int nq, epb, lay;
 };
