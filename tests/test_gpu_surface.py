@@ -187,6 +187,79 @@ def test_rhs_vs_oracle(sv, oracle_mod, Nq):
         assert err(host(out32), b32.astype(np.float64) + ref32).max() <= TOL32, (Nq, with_ref)
 
 
+def err_per_element(out, ref):
+    """|out_b - ref_b| / max|ref_b| maximised within each element: [Ne, field],
+    each element judged at its own scale."""
+    d = np.abs(np.asarray(out, np.float64) - ref).max(axis=2)
+    m = np.abs(ref).max(axis=2)
+    return np.where(m > 0, d / np.where(m > 0, m, 1.0), 0.0)
+
+
+EPS32 = 2.0 ** -23
+
+
+def fp32_full_pressure_gate(w32, ref, surface):
+    """Per element and field, the gate of the FP32 form without a reference
+    state: the full pressure p = p0 (R Theta / p0)^gamma is rounded in FP32 to
+    a few ulp (log, multiply, exp) and enters the momentum fluxes; the
+    contractions pass its rounding on amplified by at most
+    3 max_i sum_n |D_in| max|g| max(1/J) within the element, and the face
+    term (v + s) by at most 3 (N (N + 1) / 2) max|g| max(1/J) more.  Gate for
+    U1..U3: TOL32 + 4 eps32 max|p| amp / max|ref_b|; other fields TOL32."""
+    x = w32.phys.R * np.asarray(w32.q[:, 4], np.float64) / w32.phys.p0
+    p_max = (w32.phys.p0 * x ** w32.phys.gamma).max(axis=1)
+    g = np.asarray(w32.geo, np.float64)
+    D = np.asarray(w32.D, np.float64)
+    Nq = D.shape[0]
+    spread = np.abs(D).sum(axis=1).max() + (Nq - 1) * Nq / 2.0 * surface
+    amp = 3 * spread * np.abs(g[:, :9]).max(axis=(1, 2)) * g[:, 9].max(axis=1)
+    m = np.abs(ref).max(axis=2)
+    gate = np.full(m.shape, TOL32)
+    gate[:, 1:4] += 4 * EPS32 * (p_max * amp)[:, None] / np.where(m[:, 1:4] > 0, m[:, 1:4], 1.0)
+    return gate
+
+
+@pytest.mark.parametrize("Nq", [4, 8])
+def test_pressure_over_decades_of_theta(sv, oracle_mod, Nq):
+    """Theta_ref at a scale drawn per element over five decades (R Theta / p0
+    from about 1e-3 to 6e2 at atmospheric constants, so the logarithm of the
+    equation of state runs through binary exponents from -9 to +10) and
+    Theta / Theta_ref from 0.5 to 2 at every node (log1p far from small
+    arguments in FP32): the volume term and v + s against the oracle, each
+    element judged at its own scale, FP64 and FP32, with and without the
+    reference state."""
+    w = I.warped_workload(N=Nq - 1, n_side=3, k=360 + Nq)
+    rng = np.random.default_rng(3600 + Nq)
+    scale = 10.0 ** rng.uniform(0.0, 5.0, size=(w.Ne, 1))
+    w.theta_ref = scale * rng.uniform(0.8, 1.25, size=w.theta_ref.shape)
+    w.q[:, 4] = w.theta_ref * rng.uniform(0.5, 2.0, size=w.theta_ref.shape)
+    ph = w.phys.as_tuple()
+    w32 = I.to_fp32(w)
+    u = I.upcast(w32)
+    for with_ref in (True, False):
+        rr, tr = (w.rho_ref, w.theta_ref) if with_ref else (None, None)
+        v = oracle_mod.volume_rhs(w.D, w.geo, w.q, rr, tr, ph)
+        got = sv.volume_rhs(dev(w.q), dev(w.geo), dev(w.D), dev(rr), dev(tr), ph)
+        e = err_per_element(host(got), v).max(axis=0)
+        assert e.max() <= TOL64, ("volume", Nq, with_ref, e)
+        vs = oracle_vs(oracle_mod, w, with_ref=with_ref)
+        e = err_per_element(host(run_rhs(sv, w, with_ref=with_ref)), vs).max(axis=0)
+        assert e.max() <= TOL64, ("v + s", Nq, with_ref, e)
+        v32 = oracle_mod.volume_rhs(u.D, u.geo, u.q, u.rho_ref if with_ref else None,
+                                    w.theta_ref if with_ref else None, ph)
+        got32 = sv.volume_rhs(dev(w32.q), dev(w32.geo), dev(w32.D),
+                              dev(w32.rho_ref) if with_ref else None,
+                              dev(w.theta_ref) if with_ref else None, ph)
+        e32 = err_per_element(host(got32), v32)
+        gate = TOL32 if with_ref else fp32_full_pressure_gate(w32, v32, surface=False)
+        assert np.all(e32 <= gate), ("volume fp32", Nq, with_ref, e32.max(axis=0))
+        vs32 = oracle_vs(oracle_mod, w, with_ref=with_ref, fp32=True)
+        e32 = err_per_element(host(run_rhs(sv, w, with_ref=with_ref, fp32=True)), vs32)
+        gate = TOL32 if with_ref else fp32_full_pressure_gate(w32, vs32, surface=True)
+        assert np.all(e32 <= gate), ("v + s fp32", Nq, with_ref, e32.max(axis=0))
+        print("decades of Theta Nq", Nq, "ref", with_ref, "fp32 err", e32.max(axis=0))
+
+
 @pytest.mark.parametrize("Nq", [3, 8])
 def test_rhs_boundary_faces(sv, oracle_mod, Nq):
     """A sub-mesh of the box with boundary faces (neighbours outside it, and
