@@ -363,6 +363,12 @@ class VolumeRHS(torch.autograd.Function):
         return g, None, None, None, None, None
 
 
+def _block_dtype(blocks: Sequence[dict]) -> torch.dtype:
+    if not blocks:
+        raise ValueError("at least one block is required")
+    return blocks[0]["q"].dtype
+
+
 def _blocks(blocks: Sequence[dict], dtype: torch.dtype):
     arr = (sem_block * len(blocks))()
     keep = []
@@ -385,7 +391,7 @@ class BatchPlan:
 
     def __init__(self, blocks: Sequence[dict], phys=None, autotune: bool = False,
                  use_cache: bool = False, stream=None):
-        self.dtype = blocks[0]["q"].dtype
+        self.dtype = _block_dtype(blocks)
         arr, self._keep = _blocks(blocks, self.dtype)
         self._phys = _phys(phys)
         flags = (SEM_PLAN_AUTOTUNE if autotune else 0) | (SEM_PLAN_USE_CACHE if use_cache else 0)
@@ -418,7 +424,7 @@ def batch_rhs_static(blocks: Sequence[dict], phys=None, stream=None) -> None:
     """The mixed-order batch of ``BatchPlan(blocks).execute()`` (built-in
     tile shapes) in one call that allocates no device memory; ``blocks`` as
     for ``BatchPlan``, every block's ``rhs`` overwritten."""
-    dtype = blocks[0]["q"].dtype
+    dtype = _block_dtype(blocks)
     arr, _ = _blocks(blocks, dtype)
     ph = _phys(phys)
     _check(lib().sem_batch_rhs_static(arr, len(blocks), _code(dtype), ctypes.byref(ph),

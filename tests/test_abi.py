@@ -160,6 +160,13 @@ def test_batch_rhs_static_validation(L, sv):
     assert L.sem_batch_rhs_static(bad, 1, 0, ctypes.byref(ph), None) == -1
 
 
+def test_binding_rejects_an_empty_block_list(sv):
+    with pytest.raises(ValueError, match="at least one block"):
+        sv.batch_rhs_static([])
+    with pytest.raises(ValueError, match="at least one block"):
+        sv.BatchPlan([])
+
+
 def test_rk3_validation(L, sv):
     ph = sv.sem_phys(1e5, 1.4, 287.0, 9.81)
     out = ctypes.c_void_p()
